@@ -1,0 +1,126 @@
+/*
+ * stim_gpu.h -- C ABI of the MI355X batched Pauli-frame sampler.
+ *
+ * The library implements the bulk-sampling path of Gidney, "Stim: a fast
+ * stabilizer circuit simulator" (arXiv:2103.02202):
+ *   - circuits in the line format of Sec. 5.10 (one operation per line,
+ *     '#' comments, broadcasting over targets, REPEAT N { ... });
+ *   - one noiseless reference sample from an inverse stabilizer tableau
+ *     (Sec. 4), computed on the host;
+ *   - Pauli-frame simulation of many shots at once (Sec. 3) on the GPU, with
+ *     the frame stored as one bit per shot, shots along the fast axis
+ *     (Sec. 5.1), X bits and Z bits in separate planes;
+ *   - measurement results = reference XOR frame x bit (Sec. 3);
+ *   - detection events = XOR of each detector's measurement flips (Sec. 5.6).
+ *
+ * Output layout (all sampling calls): row-major [rows][W] uint64 words with
+ * W = ceil(num_shots / 64).  Bit j of word w of a row is shot
+ * shot_offset + 64 w + j, least significant bit first as in the b8 format of
+ * Sec. 5.11; bits past num_shots are zero.
+ *
+ * Random bits: every random choice is a pure function of (seed, flat
+ * instruction index, target slot, absolute 64-shot word), drawn from
+ * Philox4x64-10.  Results therefore do not depend on how shots are split
+ * across calls, tiles or launches: sampling shots [a, b) in one call gives the
+ * same bits as the corresponding slice of a larger call.
+ *
+ * Ownership: the library owns circuit handles and the device copies cached in
+ * them (one per device, uploaded on first use).  The caller owns every output
+ * buffer and every stream.  All pointers named out_* are device pointers.
+ *
+ * Errors: every int-returning call returns STIM_OK (0) or a negative code and
+ * sets a thread-local message readable with stim_last_error().  No C++
+ * exception crosses this interface.
+ *
+ * Concurrency: compile and reference calls are synchronous host work.
+ * Sampling calls enqueue work on `hip_stream` (a hipStream_t; NULL = the
+ * legacy default stream) and return without waiting, except that the first
+ * call on a device uploads the circuit (hipMemcpyAsync on that stream).  After
+ * stim_reference_sample has run, a handle is read-only and may be used from
+ * several streams at once.
+ */
+#ifndef STIM_GPU_H
+#define STIM_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  STIM_OK = 0,
+  STIM_E_PARSE = -1,        /* malformed circuit text; message has the line */
+  STIM_E_INVALID_ARG = -2,  /* null / misaligned / out-of-range argument */
+  STIM_E_OOM = -3,          /* host or device allocation failed */
+  STIM_E_DEVICE = -4,       /* a HIP call failed */
+  STIM_E_UNSUPPORTED = -5   /* unknown gate, non-Pauli channel, size limit */
+};
+
+typedef struct stim_circuit stim_circuit;   /* opaque, library-owned */
+
+/* Parses and compiles circuit text (Sec. 5.10).  `text` need not be
+ * NUL-terminated.  On success *out receives a new handle.  Supported:
+ * I X Y Z H H_XY H_YZ S S_DAG SQRT_X SQRT_X_DAG SQRT_Y SQRT_Y_DAG CX CY CZ SWAP
+ * R M MR X_ERROR Y_ERROR Z_ERROR DEPOLARIZE1 DEPOLARIZE2 DETECTOR
+ * OBSERVABLE_INCLUDE TICK QUBIT_COORDS SHIFT_COORDS REPEAT (and the aliases
+ * CNOT ZCX ZCY ZCZ H_XZ SQRT_Z SQRT_Z_DAG RZ MZ MRZ).  Unknown gates give
+ * STIM_E_UNSUPPORTED; syntax errors STIM_E_PARSE. */
+int stim_compile(const char *text, size_t len, stim_circuit **out);
+
+/* Frees a handle and its device copies.  NULL is ignored.  The caller must
+ * ensure no sampling call using the handle is still running. */
+void stim_circuit_free(stim_circuit *c);
+
+/* Sizes of the compiled circuit.  Any output pointer may be NULL.
+ * num_gate_targets counts each one-qubit Clifford / R / M / MR target and each
+ * two-qubit Clifford pair once (noise and annotations excluded). */
+int stim_circuit_shape(const stim_circuit *c, uint64_t *num_qubits, uint64_t *num_measurements,
+                       uint64_t *num_detectors, uint64_t *num_observables, uint64_t *num_gate_targets);
+
+/* The canonical noiseless reference sample (Sec. 4, inverse tableau): every
+ * random measurement result -- including the measurement implied by a reset --
+ * is taken to be 0; deterministic results are what they are.  Computed on the
+ * first call and cached in the handle.  ref_out: host buffer of
+ * ceil(num_measurements / 64) uint64 words (bit m = measurement m), or NULL
+ * to only compute and cache. */
+int stim_reference_sample(stim_circuit *c, uint64_t *ref_out);
+
+/* Samples measurement records of shots [shot_offset, shot_offset + num_shots)
+ * (Sec. 3).  out_meas: device buffer [num_measurements][W] uint64.
+ * shot_offset must be a multiple of 64; num_shots > 0.  Computes the reference
+ * sample first if it is not cached yet. */
+int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
+                      uint64_t *out_meas, void *hip_stream);
+
+/* Samples detection events (Sec. 5.6) and observable flips of the same shots.
+ * out_det: device [num_detectors][W]; out_obs: device [num_observables][W] or
+ * NULL.  Event = XOR of the detector's measurement flips (the reference bits
+ * cancel because detectors are deterministic in the noiseless circuit). */
+int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
+                         uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
+
+/* One request of a batched launch. mode 0: out0 = measurement record
+ * (as stim_frame_sample); mode 1: out0 = detection events, out1 = observable
+ * flips or NULL (as stim_detector_sample). */
+typedef struct {
+  stim_circuit *c;
+  uint64_t seed, shot_offset, num_shots;
+  int mode;
+  uint64_t *out0, *out1;
+} stim_request;
+
+/* Samples many requests (different circuits, shot counts and modes) in one
+ * persistent launch on `hip_stream`; bit-identical to calling the single-
+ * request functions one by one. */
+int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *stim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STIM_GPU_H */

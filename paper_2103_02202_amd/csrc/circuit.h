@@ -1,0 +1,100 @@
+// Host-side circuit representation of the sampler: parse tree, compiled device
+// program and the metadata the kernels need.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace stimgpu {
+
+// Operation vocabulary (Sec. 5.10 format).  Frame rules per Clifford are the
+// unsigned xz-linear maps of their tableaus (Sec. 3, Sec. 5.1):
+//   swap(x, z): H, SQRT_Y, SQRT_Y_DAG      z ^= x: S, S_DAG, H_XY
+//   x ^= z: SQRT_X, SQRT_X_DAG, H_YZ       none: I, X, Y, Z
+enum Gate : uint8_t {
+  G_I, G_X, G_Y, G_Z, G_H, G_H_XY, G_H_YZ, G_S, G_S_DAG, G_SQRT_X, G_SQRT_X_DAG,
+  G_SQRT_Y, G_SQRT_Y_DAG, G_CX, G_CY, G_CZ, G_SWAP, G_R, G_M, G_MR,
+  G_X_ERROR, G_Y_ERROR, G_Z_ERROR, G_DEPOLARIZE1, G_DEPOLARIZE2,
+  G_DETECTOR, G_OBSERVABLE_INCLUDE, G_TICK, G_QUBIT_COORDS, G_SHIFT_COORDS,
+  G_NUM
+};
+
+bool gate_is_two_qubit(Gate g);
+bool gate_is_noise(Gate g);
+bool gate_is_clifford(Gate g);
+const char *gate_name(Gate g);
+
+// One line of circuit text, or a REPEAT block.
+struct Node {
+  bool repeat = false;
+  uint64_t reps = 0;
+  std::vector<Node> body;
+  Gate gate = G_TICK;
+  double p = 0;                    // noise probability / observable index
+  std::vector<uint32_t> targets;   // qubits, or lookbacks k of rec[-k]
+  int line = 0;
+};
+
+// Kernel operation codes.
+enum OpCode : uint32_t {
+  OP_INIT = 0,      // x := 0, z := ZRAND for every qubit (targets = all qubits)
+  OP_SWAP_XZ,       // H-like
+  OP_Z_XOR_X,       // S-like
+  OP_X_XOR_Z,       // SQRT_X-like
+  OP_CX, OP_CY, OP_CZ, OP_SWAP,
+  OP_R, OP_M, OP_MR,
+  OP_NOISE_X, OP_NOISE_Y, OP_NOISE_Z, OP_NOISE_DEP1, OP_NOISE_DEP2,
+  OP_LOOP_BEGIN, OP_LOOP_END,
+  OP_COUNT
+};
+
+// Flag in OpCode word: this op starts a new instruction (advance the flat
+// index) rather than continuing the previous one after a split.
+constexpr uint32_t OPF_NEW_INSTR = 1u << 16;
+// Flag on a target word: the ZRAND of this collapse target is never read
+// before it is overwritten, so it need not be drawn.
+constexpr uint32_t TGT_DEAD_ZRAND = 1u << 31;
+constexpr uint32_t TGT_QUBIT_MASK = ~TGT_DEAD_ZRAND;
+
+// Device program entry (32 bytes).
+struct DevOp {
+  uint32_t code;    // OpCode | flags
+  uint32_t lead;    // flat instructions (annotations, Pauli gates) skipped before it
+  uint32_t n;       // targets (qubits), or pairs for two-qubit ops
+  uint32_t toff;    // offset of the first target word in the target array
+  uint32_t slot0;   // slot (position in the user instruction) of the first target
+  uint32_t aux;     // noise: threshold row; loop begin: repetitions; loop end: begin pc
+  uint32_t aux2;    // loop begin: pc of the matching loop end
+  uint32_t pad;
+};
+
+struct Program {
+  std::vector<DevOp> ops;
+  std::vector<uint32_t> targets;
+  std::vector<uint64_t> thresholds;        // [rows][64]
+  std::vector<uint32_t> det_offsets;       // CSR over detectors, size D + 1
+  std::vector<uint32_t> det_indices;       // absolute measurement indices
+  std::vector<uint32_t> obs_offsets;       // CSR over observables, size L + 1
+  std::vector<uint32_t> obs_indices;
+  uint64_t num_qubits = 0, num_measurements = 0, num_detectors = 0, num_observables = 0;
+  uint64_t num_gate_targets = 0, num_noise_targets = 0, num_instructions = 0;
+  uint32_t max_loop_depth = 0;
+};
+
+struct CompileError {
+  int code;          // STIM_E_*
+  std::string msg;
+};
+
+// Parses text into a tree (throws CompileError).
+std::vector<Node> parse_circuit(const std::string &text);
+// Lowers a tree into the device program (throws CompileError).
+Program compile_program(const std::vector<Node> &tree);
+// Canonical reference sample (Sec. 4); bit m of the result = measurement m.
+std::vector<uint64_t> reference_sample(const std::vector<Node> &tree, uint64_t num_qubits,
+                                       uint64_t num_measurements);
+// Gap-sampling thresholds t[0..63] of probability p (exact integer recurrence).
+void noise_thresholds(double p, uint64_t *t);
+
+}  // namespace stimgpu

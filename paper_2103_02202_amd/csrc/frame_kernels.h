@@ -1,0 +1,38 @@
+// Launch interface of the frame kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "circuit.h"
+
+namespace stimgpu {
+
+struct FrameParams {
+  const DevOp *ops;
+  uint32_t num_ops;
+  uint32_t num_qubits;
+  const uint32_t *targets;
+  const uint64_t *thresholds;   // [rows][64]
+  const uint64_t *ref;          // reference bits; NULL: write raw flips
+  uint64_t seed;
+  uint64_t word0;               // absolute word index of local word 0
+  uint64_t num_words;           // W
+  uint64_t tail_mask;           // valid bits of local word W - 1
+  uint64_t *out;                // [M][out_stride]
+  uint64_t out_stride;
+  uint64_t *scratch;            // global frame slices when not in LDS
+};
+
+struct FrameConfig {
+  int tile_words;               // T: 1, 2, 4, 8, 16 or 32
+  bool in_lds;
+  uint32_t threads;
+};
+
+hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_t stream);
+hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,
+                         uint32_t rows, uint64_t *out, hipStream_t stream);
+
+}  // namespace stimgpu

@@ -1,0 +1,138 @@
+// Counter-based random bits for the frame kernels.
+//
+// Generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11).  Key = (seed, KEY_HI).  Each call maps
+// a 256-bit counter to four 64-bit outputs ("lanes").
+//
+// Counter layout for one random quantity:
+//   c0 = flat instruction index (all ones for the initial frame randomisation)
+//   c1 = target slot, or slot / 4 (Z randomisation), or slot / 16 (noise prefix)
+//   c2 = absolute 64-shot word index (shot / 64)
+//   c3 = purpose << 32 | call number
+//
+// Z randomisation after a collapse (Sec. 3): the 64 bits for (instr, slot,
+// word) are lane slot % 4 of call (instr, slot / 4, word, 1 << 32).
+//
+// Pauli noise by geometric gaps (Sec. 5.5), per (instr, slot, word): a
+// sequence of 64-bit draws d_0, d_1, ...; d_0's top 16 bits are chunk slot % 16
+// (bits 16 (k % 4) .. of lane k / 4) of call (instr, slot / 16, word, 2 << 32)
+// and its low 48 bits come from lane 0 of call (instr, slot, word, 3 << 32);
+// d_j (j >= 1) is lane j % 4 of call (instr, slot, word, 3 << 32 | j / 4).
+// Starting at position 0, each gap draw u advances the position by
+// G = #{g in 1..64 : u < t[g]}; a position below 64 is an error, followed (for
+// depolarizing channels) by a choice draw c = floor(u K / 2^64), then the
+// position steps past it.  Because the first draw's high bits come from a call
+// shared by 16 slots, most words are proved error-free without evaluating the
+// slot's own call.
+#pragma once
+
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define STIM_HD __host__ __device__ __forceinline__
+#else
+#define STIM_HD inline
+#endif
+
+namespace stimgpu {
+
+constexpr uint64_t KEY_HI = 0x5354494D5F465241ull;
+constexpr uint64_t PURPOSE_ZRAND = 1, PURPOSE_NOISE_PREFIX = 2, PURPOSE_NOISE_DETAIL = 3;
+constexpr uint64_t INIT_INSTRUCTION = ~0ull;
+constexpr uint64_t MASK48 = (1ull << 48) - 1;
+
+struct U64x4 { uint64_t v[4]; };
+
+STIM_HD uint64_t mul_hi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+STIM_HD U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    uint64_t lo0 = M0 * c0, hi0 = mul_hi64(M0, c0);
+    uint64_t lo1 = M1 * c2, hi1 = mul_hi64(M1, c2);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  return U64x4{{c0, c1, c2, c3}};
+}
+
+STIM_HD uint64_t lane_of(const U64x4 &r, uint32_t lane) {
+  return lane == 0 ? r.v[0] : lane == 1 ? r.v[1] : lane == 2 ? r.v[2] : r.v[3];
+}
+
+STIM_HD uint64_t zrand_word(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word) {
+  U64x4 r = philox4x64_10(instr, slot >> 2, word, PURPOSE_ZRAND << 32, seed, KEY_HI);
+  return lane_of(r, (uint32_t)(slot & 3));
+}
+
+STIM_HD uint64_t noise_prefix16(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word) {
+  U64x4 r = philox4x64_10(instr, slot >> 4, word, PURPOSE_NOISE_PREFIX << 32, seed, KEY_HI);
+  uint32_t k = (uint32_t)(slot & 15);
+  return (lane_of(r, k >> 2) >> (16 * (k & 3))) & 0xFFFF;
+}
+
+// G = #{g in 1..64 : u < t[g-1]} for non-increasing t.
+STIM_HD int gap_length(uint64_t u, const uint64_t *t) {
+  int lo = 0, hi = 64;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (u < t[mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Error masks of one noise site on one word.  K = 0: single mask in m[0];
+// K = 3: DEPOLARIZE1, m[0] = x flips, m[1] = z flips (choice 0 X, 1 Y, 2 Z);
+// K = 15: DEPOLARIZE2, m[0..3] = x_a, z_a, x_b, z_b flips of Pauli choice + 1.
+template <int K>
+STIM_HD void noise_masks(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
+                         uint64_t v16, uint64_t m[4]) {
+  // Four draws per call, kept in named registers (no indexed local array).
+  uint64_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  uint32_t j = 0;
+  auto draw = [&]() -> uint64_t {
+    uint32_t lane = j & 3;
+    if (lane == 0) {
+      U64x4 r = philox4x64_10(instr, slot, word, (PURPOSE_NOISE_DETAIL << 32) | (j >> 2), seed, KEY_HI);
+      b0 = r.v[0]; b1 = r.v[1]; b2 = r.v[2]; b3 = r.v[3];
+    }
+    j++;
+    return lane == 0 ? b0 : lane == 1 ? b1 : lane == 2 ? b2 : b3;
+  };
+  uint64_t u = (v16 << 48) | (draw() & MASK48);
+  int pos = 0;
+  while (true) {
+    pos += gap_length(u, t);
+    if (pos >= 64) break;
+    uint64_t bit = 1ull << pos;
+    if (K == 0) {
+      m[0] |= bit;
+    } else {
+      uint64_t c = mul_hi64(draw(), (uint64_t)K);
+      if (K == 3) {
+        if (c <= 1) m[0] |= bit;
+        if (c >= 1) m[1] |= bit;
+      } else {
+        uint64_t v = c + 1;
+        if (v & 1) m[0] |= bit;
+        if (v & 2) m[1] |= bit;
+        if (v & 4) m[2] |= bit;
+        if (v & 8) m[3] |= bit;
+      }
+    }
+    if (++pos >= 64) break;
+    u = draw();
+  }
+}
+
+}  // namespace stimgpu

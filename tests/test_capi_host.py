@@ -1,0 +1,109 @@
+"""Host-side tests of the C ABI (no GPU needed).
+
+* The library loads and exports every function declared in include/stim_gpu.h.
+* stim_compile / stim_circuit_shape / stim_reference_sample (host-only calls)
+  agree with the oracle: shapes, and the canonical reference bit for bit.
+* Error codes for malformed input and bad sampling arguments.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02202_amd import stim_gpu as sg
+from paper_2103_02202_amd import workloads as wl
+from circuit_gen import random_circuit
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "stim_gpu.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stim_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "stim_frame_sample" in names and "stim_batch_sample" in names
+    L = sg.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def unpack_ref(words, m):
+    bits = np.array(words, dtype=np.uint64)
+    return np.unpackbits(bits.view(np.uint8), bitorder="little")[:m] if m else np.zeros(0, np.uint8)
+
+
+CASES = {
+    "surface_d3": lambda: wl.surface_code(3, 3, 1e-3),
+    "surface_d7": lambda: wl.surface_code(7, 7, 1e-3),
+    "surface_d15": lambda: wl.surface_code(15, 15, 1e-3),
+    "repetition": wl.repetition_code_example,
+    "teleport": wl.teleportation_example,
+    "random_clifford_64": lambda: wl.random_clifford(64, 40, seed=3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_shape_and_reference_match_oracle(name):
+    text = CASES[name]()
+    c, o = sg.Circuit(text), oracle.Circuit(text)
+    assert (c.num_qubits, c.num_measurements, c.num_detectors, c.num_observables, c.num_gate_targets) == \
+        (o.num_qubits, o.num_measurements, o.num_detectors, o.num_observables, o.num_gate_targets)
+    assert np.array_equal(unpack_ref(c.reference(), c.num_measurements), o.reference())
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_reference_matches_oracle_on_random_circuits(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.integers(2, 40))
+    text = random_circuit(n, int(rng.integers(20, 300)), seed=9000 + seed, noise=True)
+    c, o = sg.Circuit(text), oracle.Circuit(text)
+    assert np.array_equal(unpack_ref(c.reference(), c.num_measurements), o.reference())
+
+
+def test_surface_closed_form_counts():
+    for d in (3, 5, 9):
+        c = sg.Circuit(wl.surface_code(d, d, 1e-3))
+        k = wl.surface_code_counts(d, d)
+        assert (c.num_qubits, c.num_gate_targets, c.num_measurements, c.num_detectors) == \
+            (k["num_qubits"], k["num_gate_targets"], k["num_measurements"], k["num_detectors"])
+
+
+@pytest.mark.parametrize("text,code", [
+    ("FOO 0", sg.STIM_E_UNSUPPORTED),
+    ("H 0 x", sg.STIM_E_PARSE),
+    ("CX 0", sg.STIM_E_PARSE),
+    ("CX 2 2", sg.STIM_E_PARSE),
+    ("REPEAT 0 {\nH 0\n}", sg.STIM_E_PARSE),
+    ("REPEAT 3 {\nH 0", sg.STIM_E_PARSE),
+    ("}", sg.STIM_E_PARSE),
+    ("X_ERROR(1.5) 0", sg.STIM_E_PARSE),
+    ("DEPOLARIZE1 0", sg.STIM_E_PARSE),
+    ("M 0\nDETECTOR rec[-2]", sg.STIM_E_PARSE),
+    ("H(0.5) 0", sg.STIM_E_PARSE),
+    ("AMPLITUDE_DAMP(0.1) 0", sg.STIM_E_UNSUPPORTED),
+])
+def test_compile_errors(text, code):
+    with pytest.raises(sg.StimError) as e:
+        sg.Circuit(text)
+    assert e.value.code == code
+    if code == sg.STIM_E_PARSE:
+        assert "line" in str(e.value)
+
+
+def test_sampling_argument_errors_need_no_gpu():
+    c = sg.Circuit("M 0\n")
+    L = sg.lib()
+    h = ctypes.c_void_p(c.handle)
+    # misaligned offset, zero shots and a null handle fail before any device work
+    assert L.stim_frame_sample(h, 0, 3, 64, ctypes.c_void_p(1), None) == sg.STIM_E_INVALID_ARG
+    assert L.stim_frame_sample(h, 0, 0, 0, ctypes.c_void_p(1), None) == sg.STIM_E_INVALID_ARG
+    assert L.stim_frame_sample(None, 0, 0, 64, ctypes.c_void_p(1), None) == sg.STIM_E_INVALID_ARG
+    assert L.stim_detector_sample(h, 0, 65, 64, None, None, None) == sg.STIM_E_INVALID_ARG
+    assert L.stim_batch_sample(None, 1, None) == sg.STIM_E_INVALID_ARG

@@ -1,0 +1,183 @@
+"""GPU parity: the HIP sampler against the oracle, bit for bit (tolerance 0).
+
+Every case names itself on stdout before touching the GPU.  Sizes span several
+tiles and ragged tails; large configurations are checked on sampled shot
+slices the oracle computes alone (exact, because random bits are keyed by
+absolute shot).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02202_amd import workloads as wl
+from circuit_gen import random_circuit
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_2103_02202_amd import stim_gpu
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    stim_gpu.lib()
+    return stim_gpu
+
+
+def gpu_meas(sg, c, seed, shots, offset=0):
+    out = c.sample(seed, shots, shot_offset=offset)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+def gpu_det(sg, c, seed, shots, offset=0):
+    det, obs = c.detect(seed, shots, shot_offset=offset)
+    torch.cuda.synchronize()
+    return det.cpu().numpy().view(np.uint64), obs.cpu().numpy().view(np.uint64)
+
+
+def check_meas(sg, text, seed, shots, offset=0):
+    c = sg.Circuit(text)
+    o = oracle.Circuit(text)
+    got = gpu_meas(sg, c, seed, shots, offset)
+    want = o.sample(seed, offset, shots, meas=True)["meas"]
+    assert got.shape == want.shape
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"first mismatch at (measurement, word) {bad[0].tolist()}"
+
+
+def check_det(sg, text, seed, shots, offset=0):
+    c = sg.Circuit(text)
+    o = oracle.Circuit(text)
+    det, obs = gpu_det(sg, c, seed, shots, offset)
+    want = o.sample(seed, offset, shots, det=True, obs=True, meas=False)
+    assert np.array_equal(det, want["det"])
+    assert np.array_equal(obs, want["obs"])
+
+
+@pytest.mark.parametrize("shots", [1024, 1000, 1, 65, 4097])
+def test_surface_d3_measurements(sg, shots):
+    announce("surface d3", shots)
+    check_meas(sg, wl.surface_code(3, 3, 1e-3), 0, shots)
+
+
+def test_surface_d3_detectors(sg):
+    announce("surface d3 detectors")
+    check_det(sg, wl.surface_code(3, 3, 1e-3), 0, 1024)
+
+
+@pytest.mark.parametrize("p", [1e-3, 1e-2, 0.2])
+def test_surface_d5_high_noise(sg, p):
+    announce("surface d5", p)
+    text = wl.surface_code(5, 5, p)
+    check_meas(sg, text, 7, 3000)
+    check_det(sg, text, 7, 3000)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_noisy_circuits(sg, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.integers(2, 60))
+    text = random_circuit(n, int(rng.integers(20, 250)), seed=7000 + seed, noise=True,
+                          p=float(rng.choice([1e-3, 0.05, 0.5, 1.0])))
+    shots = int(rng.integers(1, 5000))
+    announce("random", seed, n, shots)
+    check_meas(sg, text, seed, shots)
+
+
+def test_paper_examples(sg):
+    announce("appendix examples")
+    check_meas(sg, wl.repetition_code_example(), 3, 1024)
+    check_meas(sg, wl.teleportation_example(), 3, 2048)
+
+
+def test_repeat_nesting_and_annotations(sg):
+    announce("nested repeat")
+    text = ("H 0 1\nTICK\nREPEAT 3 {\n  DEPOLARIZE1(0.1) 0 1 2\n  REPEAT 2 {\n    CX 0 1 1 2\n    TICK\n"
+            "    X_ERROR(0.2) 2\n  }\n  MR 2\n  DETECTOR rec[-1]\n  M 0 0\n}\nM 0 1 2\n"
+            "OBSERVABLE_INCLUDE(1) rec[-1] rec[-2]\n")
+    check_meas(sg, text, 11, 777)
+    check_det(sg, text, 11, 777)
+
+
+def test_shot_offset_slices(sg):
+    announce("shot offsets")
+    text = wl.surface_code(5, 3, 0.01)
+    for off, shots in [(64, 100), (4096, 64), (1 << 20, 3000), ((1 << 40) + 128, 500)]:
+        check_meas(sg, text, 5, shots, off)
+
+
+@pytest.mark.parametrize("tile,placement", [("1", "lds"), ("4", "lds"), ("32", "lds"),
+                                            ("2", "global"), ("16", "global")])
+def test_tiling_does_not_change_results(sg, tile, placement, monkeypatch):
+    announce("tiling", tile, placement)
+    monkeypatch.setenv("STIM_TILE_WORDS", tile)
+    monkeypatch.setenv("STIM_FRAME_PLACEMENT", placement)
+    text = wl.surface_code(5, 5, 0.01)
+    check_meas(sg, text, 2, 5000)
+    check_det(sg, text, 2, 5000)
+
+
+def test_surface_d15_slices_of_full_run(sg):
+    """d=15, 2^20 shots (the full configuration) on the GPU; slices checked by
+    the oracle, everything checked for all-zero tails."""
+    announce("surface d15 full")
+    text = wl.surface_code(15, 15, 1e-3)
+    c = sg.Circuit(text)
+    o = oracle.Circuit(text)
+    shots = 1 << 20
+    full = c.sample(0, shots)
+    det, obs = c.detect(0, shots)
+    torch.cuda.synchronize()
+    for w0 in (0, 5000, 16383):
+        sl = full[:, w0:w0 + 1].cpu().numpy().view(np.uint64)
+        want = o.sample(0, 64 * w0, 64, meas=True, det=True, obs=True)
+        assert np.array_equal(sl, want["meas"])
+        assert np.array_equal(det[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["det"])
+        assert np.array_equal(obs[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["obs"])
+
+
+def test_surface_d49_noiseless_detectors_zero_and_noisy_slices(sg):
+    announce("surface d49")
+    shots = 65536
+    c0 = sg.Circuit(wl.surface_code(49, 49, 0.0))
+    det, obs = c0.detect(0, shots)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(det)) == 0
+    assert int(torch.count_nonzero(obs)) == 0
+    text = wl.surface_code(49, 49, 1e-3)
+    c = sg.Circuit(text)
+    o = oracle.Circuit(text)
+    full = c.sample(0, shots)
+    torch.cuda.synchronize()
+    for w0 in (0, 777):
+        sl = full[:, w0:w0 + 1].cpu().numpy().view(np.uint64)
+        want = o.sample(0, 64 * w0, 64, meas=True)["meas"]
+        assert np.array_equal(sl, want)
+
+
+def test_determinism_run_twice(sg):
+    announce("determinism")
+    c = sg.Circuit(wl.surface_code(9, 9, 5e-3))
+    a = gpu_meas(sg, c, 4, 20000)
+    b = gpu_meas(sg, c, 4, 20000)
+    assert np.array_equal(a, b)
+
+
+def test_device_pointer_validation(sg):
+    announce("pointer validation")
+    import ctypes
+    c = sg.Circuit("M 0\n")
+    host = np.zeros(4, dtype=np.uint64)
+    rc = sg.lib().stim_frame_sample(ctypes.c_void_p(c.handle), 0, 0, 64,
+                                    ctypes.c_void_p(host.ctypes.data), None)
+    assert rc == sg.STIM_E_INVALID_ARG
