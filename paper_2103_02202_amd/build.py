@@ -21,10 +21,11 @@ HIP_SOURCES = ["frame_kernels.hip", "capi.hip"]
 
 # Packed-FP32 instructions are kept out of every HIP object.
 # Private arrays must not be promoted into LDS: the frame slice uses it all.
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-disable-promote-alloca-to-lds"]
-HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-march=x86-64-v3"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-march=x86-64-v3", "-I", INCLUDE]
 
 
 def _run(cmd):

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/stim_gpu.h"
+#include "stim_gpu.h"
 #include "circuit.h"
 #include "frame_kernels.h"
 
@@ -110,7 +110,14 @@ bool is_device_pointer(const void *p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.type == hipMemoryTypeUnified;
 }
 
-constexpr size_t kLdsBudget = 160 * 1024;
+uint32_t threads_for(size_t frame_bytes) {
+  return frame_bytes > 80 * 1024 ? 1024 : frame_bytes > 40 * 1024 ? 512 : 256;
+}
+
+bool fits_lds(uint64_t n, int T) {
+  size_t fb = (size_t)16 * n * T;
+  return frame_lds_bytes(n, T, true, threads_for(fb)) <= kMaxLdsBytes;
+}
 
 // Picks the shot-tile width and frame placement: the widest tile whose frame
 // slice fits in LDS while still giving enough tiles to occupy the GPU.
@@ -123,25 +130,23 @@ FrameConfig choose_config(uint64_t n, uint64_t W) {
     int T = tw ? std::atoi(tw) : 1;
     if (T != 1 && T != 2 && T != 4 && T != 8 && T != 16 && T != 32) T = 1;
     bool lds = pl ? std::strcmp(pl, "global") != 0 : true;
-    if (lds && (size_t)16 * n * T > kLdsBudget) lds = false;
+    if (lds && !fits_lds(n, T)) lds = false;
     cfg.tile_words = T;
     cfg.in_lds = lds;
-    size_t bytes = (size_t)16 * n * T;
-    cfg.threads = !lds ? 256 : bytes > 80 * 1024 ? 1024 : bytes > 40 * 1024 ? 512 : 256;
+    cfg.threads = lds ? threads_for((size_t)16 * n * T) : 256;
     return cfg;
   }
   const int widths[] = {32, 16, 8, 4, 2, 1};
   for (int T : widths) {
-    size_t bytes = (size_t)16 * n * T;
     uint64_t tiles = (W + T - 1) / T;
-    if (bytes <= kLdsBudget && (tiles >= 512 || T == 1)) {
+    if (fits_lds(n, T) && (tiles >= 512 || T == 1)) {
       cfg.tile_words = T;
       cfg.in_lds = true;
-      cfg.threads = bytes > 80 * 1024 ? 1024 : bytes > 40 * 1024 ? 512 : 256;
+      cfg.threads = threads_for((size_t)16 * n * T);
       return cfg;
     }
   }
-  if ((size_t)16 * n <= kLdsBudget) return cfg;
+  if (fits_lds(n, 1)) return cfg;
   // Frame slice too large for LDS even for one word: global scratch.
   cfg.in_lds = false;
   cfg.threads = 256;

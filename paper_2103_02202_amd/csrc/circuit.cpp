@@ -16,7 +16,7 @@
 #include <map>
 #include <unordered_map>
 
-#include "../../include/stim_gpu.h"
+#include "stim_gpu.h"
 
 namespace stimgpu {
 

@@ -31,6 +31,14 @@ struct FrameConfig {
   uint32_t threads;
 };
 
+// LDS available to one workgroup on gfx950.
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+// Dynamic LDS of one frame workgroup: a 64-entry queue per wave, one
+// 64-entry threshold row, plus the frame slice (16 n T bytes) when it is held
+// in LDS.
+size_t frame_lds_bytes(uint64_t n, int T, bool in_lds, uint32_t threads);
+
 hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_t stream);
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,
                          uint32_t rows, uint64_t *out, hipStream_t stream);

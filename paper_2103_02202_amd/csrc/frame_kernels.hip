@@ -2,14 +2,20 @@
 //
 // One workgroup owns a tile of T consecutive 64-shot words and walks the whole
 // device program over it.  Shots are independent, so tiles never communicate.
-// Inside a workgroup the work of one op is spread over (target, word) items;
-// an op's targets touch pairwise distinct qubits (the compiler splits
-// instructions where a qubit repeats), so its items run in parallel and a
+// Inside a workgroup the work of one op is spread over its targets and the
+// tile's words; an op's targets touch pairwise distinct qubits (the compiler
+// splits instructions where a qubit repeats), so they run in parallel, and a
 // barrier separates consecutive ops.
 //
 // The frame slice of a tile is two bit planes, X then Z, each [n][T] uint64
 // (bit j of word w = shot 64 (tile word w) + j).  It lives in LDS when
 // 16 n T bytes fit, otherwise in a global scratch buffer.
+//
+// Random bits are drawn cooperatively: a lane evaluates one Philox call for a
+// group of slots on one word -- four slots for Z randomisation, sixteen
+// 16-bit noise prefixes -- and only the few (slot, word) pairs whose prefix
+// admits an error are queued, compacted per wave in LDS, and expanded by all
+// lanes together (geometric gaps, Sec. 5.5).
 #include <hip/hip_runtime.h>
 
 #include "circuit.h"
@@ -28,19 +34,254 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// Orders LDS traffic of one wave (all lanes of a wave run in lockstep).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exclusive prefix sum over the 64 lanes of a wave; *total gets the sum.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t lane, uint32_t *total) {
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+template <int T, bool IN_LDS>
+struct Tile {
+  uint64_t *FX, *FZ;          // frame planes
+  uint64_t *queue;            // this wave's 64-entry LDS queue
+  uint64_t tw0;               // first local word of the tile
+  int valid;                  // words of the tile inside [0, W)
+
+  __device__ __forceinline__ size_t at(uint32_t q, int j) const {
+    if constexpr (IN_LDS) return (size_t)(q * (uint32_t)T + (uint32_t)j);
+    else return (size_t)q * T + j;
+  }
+};
+
+// One out-of-line copy of the generator keeps the walker's code small enough
+// for the instruction cache.
+__device__ __forceinline__ U64x4 philox_call(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t seed) {
+  return philox4x64_10(c0, c1, c2, c3, seed, KEY_HI);
+}
+
+struct PhiloxCall {
+  __device__ U64x4 operator()(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t seed) const {
+    return philox_call(c0, c1, c2, c3, seed);
+  }
+};
+
+// Applies a noise op: prefix test per (16-slot group, word), wave-compacted
+// expansion of the surviving (slot, word) pairs.
+template <int T, bool IN_LDS>
+__device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
+                                      uint32_t code, uint64_t instr, const uint64_t *thr) {
+  const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint64_t cut = thr[63] >> 48;            // prefix below cut: no error in the word
+  // 1 / log2(1 - p) from the exact value 2^64 - t[0] ~ p 2^64; seeds the gap search.
+  const float p_est = (float)(0ull - thr[0]) * 0x1p-64f + (thr[0] == 0 ? 1.0f : 0.0f);
+  const float inv_log2_keep = 1.0f / (log1pf(-p_est) * 1.44269504088896340736f);
+  const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
+  const uint32_t g_lo = s_lo >> 4, ngroups = ((s_hi - 1) >> 4) - g_lo + 1;
+  const uint32_t cand = ngroups * T;
+  const uint32_t *tg = p.targets + op.toff;
+  for (uint32_t base = wave * 64; base < cand; base += nwaves * 64) {
+    const uint32_t c = base + lane;
+    uint32_t mask = 0;
+    U64x4 r{{0, 0, 0, 0}};
+    uint32_t g = 0;
+    int j = 0;
+    if (c < cand) {
+      g = g_lo + c / T;
+      j = (int)(c % T);
+      if (j < tl.valid) {
+        r = philox_call(instr, g, p.word0 + tl.tw0 + j, PURPOSE_NOISE_PREFIX << 32, p.seed);
+#pragma unroll
+        for (uint32_t b = 0; b < 16; b++) {
+          uint32_t s = g * 16 + b;
+          uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
+          if (s >= s_lo && s < s_hi && v16 >= cut) mask |= 1u << b;
+        }
+      }
+    }
+    uint32_t total;
+    const uint32_t first = wave_exclusive_scan((uint32_t)__builtin_popcount(mask), lane, &total);
+    for (uint32_t r0 = 0; r0 < total; r0 += 64) {
+      // Publish entries [r0, r0 + 64) of the wave's compacted list.
+      uint32_t idx = first;
+      uint32_t m = mask;
+      while (m) {
+        uint32_t b = (uint32_t)__builtin_ctz(m);
+        m &= m - 1;
+        if (idx >= r0 && idx < r0 + 64) {
+          uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
+          tl.queue[idx - r0] = ((uint64_t)(g * 16 + b) << 24) | ((uint64_t)j << 16) | v16;
+        }
+        idx++;
+      }
+      wave_sync();
+      if (r0 + lane < total) {
+        const uint64_t e = tl.queue[lane];
+        const uint32_t s = (uint32_t)(e >> 24);
+        const int jj = (int)((e >> 16) & 0xFF);
+        const uint64_t v16 = e & 0xFFFF;
+        uint64_t mk[4] = {0, 0, 0, 0};
+        noise_masks(K, p.seed, instr, s, p.word0 + tl.tw0 + jj, thr, inv_log2_keep, v16, mk, PhiloxCall());
+        const uint32_t k = s - s_lo;
+        if (code == OP_NOISE_DEP2) {
+          const uint32_t a = tg[2 * k], b = tg[2 * k + 1];
+          tl.FX[tl.at(a, jj)] ^= mk[0];
+          tl.FZ[tl.at(a, jj)] ^= mk[1];
+          tl.FX[tl.at(b, jj)] ^= mk[2];
+          tl.FZ[tl.at(b, jj)] ^= mk[3];
+        } else {
+          const uint32_t q = tg[k];
+          const uint64_t mx = code == OP_NOISE_DEP1 ? mk[0] : code != OP_NOISE_Z ? mk[0] : 0;
+          const uint64_t mz = code == OP_NOISE_DEP1 ? mk[1] : code != OP_NOISE_X ? mk[0] : 0;
+          tl.FX[tl.at(q, jj)] ^= mx;
+          tl.FZ[tl.at(q, jj)] ^= mz;
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// Collapse ops (INIT, R, M, MR): one lane per (4-slot group, word), sharing the
+// Z-randomisation call of the group.
+template <int T, bool IN_LDS>
+__device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
+                                         uint32_t code, uint64_t instr, uint64_t meas) {
+  const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
+  const uint32_t g_lo = s_lo >> 2, ngroups = ((s_hi - 1) >> 2) - g_lo + 1;
+  const uint32_t cand = ngroups * T;
+  const uint32_t *tg = p.targets + op.toff;
+  const bool measures = code == OP_M || code == OP_MR;
+  for (uint32_t c = threadIdx.x; c < cand; c += blockDim.x) {
+    const uint32_t g = g_lo + c / T;
+    const int j = (int)(c % T);
+    if (j >= tl.valid) continue;
+    const uint64_t word = p.word0 + tl.tw0 + j;
+    const uint32_t sa = g * 4 < s_lo ? s_lo : g * 4, sb = g * 4 + 4 > s_hi ? s_hi : g * 4 + 4;
+    uint32_t tv[4];
+    bool need = false;
+#pragma unroll
+    for (uint32_t u = 0; u < 4; u++) {
+      const uint32_t s = g * 4 + u;
+      tv[u] = (s >= sa && s < sb) ? tg[s - s_lo] : TGT_DEAD_ZRAND;
+      need |= !(tv[u] & TGT_DEAD_ZRAND);
+    }
+    U64x4 r{{0, 0, 0, 0}};
+    if (need) r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+#pragma unroll
+    for (uint32_t u = 0; u < 4; u++) {
+      const uint32_t s = g * 4 + u;
+      if (s < sa || s >= sb) continue;
+      const uint32_t k = s - s_lo, q = tv[u] & TGT_QUBIT_MASK;
+      const uint64_t zr = (tv[u] & TGT_DEAD_ZRAND) ? 0 : r.v[u];
+      const size_t ix = tl.at(q, j);
+      if (measures) {
+        const uint64_t m = meas + k;
+        uint64_t v = tl.FX[ix];
+        if (p.ref && ((p.ref[m >> 6] >> (m & 63)) & 1)) v = ~v;
+        if (tl.tw0 + j == p.num_words - 1) v &= p.tail_mask;
+        p.out[m * p.out_stride + tl.tw0 + j] = v;
+      }
+      if (code == OP_M) {
+        tl.FZ[ix] ^= zr;
+      } else {
+        tl.FX[ix] = 0;
+        tl.FZ[ix] = zr;
+      }
+    }
+  }
+}
+
+// Clifford ops: one item per (target, word).  A thread takes up to U items at
+// once and issues all of their target loads and frame reads before any write;
+// the items of one op touch distinct (qubit, word) cells, so this is safe and
+// hides the load latency.
+template <int T, bool IN_LDS>
+__device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
+                                         uint32_t code) {
+  constexpr int U = 4;
+  const bool two = code == OP_CX || code == OP_CY || code == OP_CZ || code == OP_SWAP;
+  const uint32_t items = op.n * T;
+  const uint32_t *tg = p.targets + op.toff;
+  uint64_t *FX = tl.FX, *FZ = tl.FZ;
+  const uint32_t stride = blockDim.x;
+  for (uint32_t base = threadIdx.x; base < items; base += U * stride) {
+    size_t ia[U], ib[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t it = base + u * stride;
+      const uint32_t k = it / T;
+      const int j = (int)(it % T);
+      ok[u] = it < items && j < tl.valid;
+      uint32_t qa = 0, qb = 0;
+      if (ok[u]) {
+        qa = tg[two ? 2 * k : k];
+        if (two) qb = tg[2 * k + 1];
+      }
+      ia[u] = tl.at(qa, j);
+      ib[u] = tl.at(qb, j);
+    }
+    uint64_t xa[U], za[U], xb[U], zb[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      xa[u] = ok[u] ? FX[ia[u]] : 0;
+      za[u] = ok[u] ? FZ[ia[u]] : 0;
+      xb[u] = ok[u] && two ? FX[ib[u]] : 0;
+      zb[u] = ok[u] && two ? FZ[ib[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (!ok[u]) continue;
+      switch (code) {
+        case OP_SWAP_XZ: FX[ia[u]] = za[u]; FZ[ia[u]] = xa[u]; break;
+        case OP_Z_XOR_X: FZ[ia[u]] = za[u] ^ xa[u]; break;
+        case OP_X_XOR_Z: FX[ia[u]] = xa[u] ^ za[u]; break;
+        case OP_CX: FX[ib[u]] = xb[u] ^ xa[u]; FZ[ia[u]] = za[u] ^ zb[u]; break;
+        case OP_CZ: FZ[ia[u]] = za[u] ^ xb[u]; FZ[ib[u]] = zb[u] ^ xa[u]; break;
+        case OP_CY:
+          FX[ib[u]] = xb[u] ^ xa[u];
+          FZ[ib[u]] = zb[u] ^ xa[u];
+          FZ[ia[u]] = za[u] ^ xb[u] ^ zb[u];
+          break;
+        default:   // SWAP
+          FX[ia[u]] = xb[u]; FZ[ia[u]] = zb[u]; FX[ib[u]] = xa[u]; FZ[ib[u]] = za[u];
+          break;
+      }
+    }
+  }
+}
+
 template <int T, bool IN_LDS>
 __global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
-  extern __shared__ uint64_t lds_frame[];
+  extern __shared__ uint64_t lds[];
+  const uint32_t nwaves = blockDim.x >> 6;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint64_t tw0 = (uint64_t)tile * T;                 // first local word of the tile
   const uint32_t n = p.num_qubits;
+  Tile<T, IN_LDS> tl;
+  tl.queue = lds + (threadIdx.x >> 6) * 64;
+  uint64_t *thr_lds = lds + nwaves * 64;         // threshold row of the current noise op
+  uint32_t thr_row = 0xFFFFFFFFu;
   uint64_t *F;
-  if constexpr (IN_LDS) F = lds_frame;
+  if constexpr (IN_LDS) F = lds + nwaves * 64 + 64;
   else F = p.scratch + (size_t)tile * 2 * n * T;
-  uint64_t *FX = F, *FZ = F + (size_t)n * T;
-  // Index of (qubit, word j) in a plane; 32-bit arithmetic suffices in LDS.
-#define FI(q) (IN_LDS ? (size_t)((uint32_t)(q) * (uint32_t)T + (uint32_t)j) : (size_t)(q) * T + j)
-  const int valid = (int)((p.num_words - tw0) < (uint64_t)T ? (p.num_words - tw0) : (uint64_t)T);
+  tl.FX = F;
+  tl.FZ = F + (size_t)n * T;
+  tl.tw0 = (uint64_t)tile * T;
+  tl.valid = (int)((p.num_words - tl.tw0) < (uint64_t)T ? (p.num_words - tl.tw0) : (uint64_t)T);
 
   uint64_t flat = 0, meas = 0;
   uint32_t loop_left[8];
@@ -68,137 +309,22 @@ __global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
     } else {
       instr = flat - 1;
     }
-    const uint32_t *tg = p.targets + op.toff;
-    const uint32_t items = op.n * T;
-    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-      const uint32_t k = it / T;
-      const int j = (int)(it % T);
-      if (j >= valid) continue;
-      const uint64_t word = p.word0 + tw0 + j;               // absolute 64-shot word
-      const uint64_t slot = (uint64_t)op.slot0 + k;
-      switch (code) {
-        case OP_INIT: {
-          uint32_t t = tg[k], q = t & TGT_QUBIT_MASK;
-          FX[FI(q)] = 0;
-          FZ[FI(q)] = (t & TGT_DEAD_ZRAND) ? 0 : zrand_word(p.seed, instr, q, word);
-          break;
-        }
-        case OP_SWAP_XZ: {
-          uint32_t q = tg[k];
-          uint64_t x = FX[FI(q)];
-          FX[FI(q)] = FZ[FI(q)];
-          FZ[FI(q)] = x;
-          break;
-        }
-        case OP_Z_XOR_X: {
-          uint32_t q = tg[k];
-          FZ[FI(q)] ^= FX[FI(q)];
-          break;
-        }
-        case OP_X_XOR_Z: {
-          uint32_t q = tg[k];
-          FX[FI(q)] ^= FZ[FI(q)];
-          break;
-        }
-        case OP_CX: {
-          uint32_t c = tg[2 * k], t = tg[2 * k + 1];
-          FX[FI(t)] ^= FX[FI(c)];
-          FZ[FI(c)] ^= FZ[FI(t)];
-          break;
-        }
-        case OP_CZ: {
-          uint32_t a = tg[2 * k], b = tg[2 * k + 1];
-          uint64_t xa = FX[FI(a)], xb = FX[FI(b)];
-          FZ[FI(a)] ^= xb;
-          FZ[FI(b)] ^= xa;
-          break;
-        }
-        case OP_CY: {
-          uint32_t c = tg[2 * k], t = tg[2 * k + 1];
-          uint64_t xc = FX[FI(c)], xt = FX[FI(t)], zt = FZ[FI(t)];
-          FX[FI(t)] = xt ^ xc;
-          FZ[FI(t)] = zt ^ xc;
-          FZ[FI(c)] ^= xt ^ zt;
-          break;
-        }
-        case OP_SWAP: {
-          uint32_t a = tg[2 * k], b = tg[2 * k + 1];
-          uint64_t xa = FX[FI(a)], za = FZ[FI(a)];
-          FX[FI(a)] = FX[FI(b)];
-          FZ[FI(a)] = FZ[FI(b)];
-          FX[FI(b)] = xa;
-          FZ[FI(b)] = za;
-          break;
-        }
-        case OP_R: {
-          uint32_t t = tg[k], q = t & TGT_QUBIT_MASK;
-          FX[FI(q)] = 0;
-          FZ[FI(q)] = (t & TGT_DEAD_ZRAND) ? 0 : zrand_word(p.seed, instr, slot, word);
-          break;
-        }
-        case OP_M:
-        case OP_MR: {
-          uint32_t t = tg[k], q = t & TGT_QUBIT_MASK;
-          const uint64_t m = meas + k;
-          uint64_t v = FX[FI(q)];
-          if (p.ref && ((p.ref[m >> 6] >> (m & 63)) & 1)) v = ~v;
-          if (tw0 + j == p.num_words - 1) v &= p.tail_mask;
-          p.out[m * p.out_stride + tw0 + j] = v;
-          if (code == OP_MR) {
-            FX[FI(q)] = 0;
-            FZ[FI(q)] = (t & TGT_DEAD_ZRAND) ? 0 : zrand_word(p.seed, instr, slot, word);
-          } else if (!(t & TGT_DEAD_ZRAND)) {
-            FZ[FI(q)] ^= zrand_word(p.seed, instr, slot, word);
-          }
-          break;
-        }
-        case OP_NOISE_X:
-        case OP_NOISE_Y:
-        case OP_NOISE_Z: {
-          const uint64_t *thr = p.thresholds + (size_t)op.aux * 64;
-          uint64_t v16 = noise_prefix16(p.seed, instr, slot, word);
-          if (v16 < (thr[63] >> 48)) break;                   // no error in these 64 shots
-          uint64_t m[4] = {0, 0, 0, 0};
-          noise_masks<0>(p.seed, instr, slot, word, thr, v16, m);
-          uint32_t q = tg[k];
-          if (code != OP_NOISE_Z) FX[FI(q)] ^= m[0];
-          if (code != OP_NOISE_X) FZ[FI(q)] ^= m[0];
-          break;
-        }
-        case OP_NOISE_DEP1: {
-          const uint64_t *thr = p.thresholds + (size_t)op.aux * 64;
-          uint64_t v16 = noise_prefix16(p.seed, instr, slot, word);
-          if (v16 < (thr[63] >> 48)) break;
-          uint64_t m[4] = {0, 0, 0, 0};
-          noise_masks<3>(p.seed, instr, slot, word, thr, v16, m);
-          uint32_t q = tg[k];
-          FX[FI(q)] ^= m[0];
-          FZ[FI(q)] ^= m[1];
-          break;
-        }
-        case OP_NOISE_DEP2: {
-          const uint64_t *thr = p.thresholds + (size_t)op.aux * 64;
-          uint64_t v16 = noise_prefix16(p.seed, instr, slot, word);
-          if (v16 < (thr[63] >> 48)) break;
-          uint64_t m[4] = {0, 0, 0, 0};
-          noise_masks<15>(p.seed, instr, slot, word, thr, v16, m);
-          uint32_t a = tg[2 * k], b = tg[2 * k + 1];
-          FX[FI(a)] ^= m[0];
-          FZ[FI(a)] ^= m[1];
-          FX[FI(b)] ^= m[2];
-          FZ[FI(b)] ^= m[3];
-          break;
-        }
-        default:
-          break;
-      }
+    if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2 && op.aux != thr_row) {
+      thr_row = op.aux;                            // uniform: every thread takes this branch
+      if (threadIdx.x < 64) thr_lds[threadIdx.x] = p.thresholds[(size_t)thr_row * 64 + threadIdx.x];
+      __syncthreads();
+    }
+    if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
+      collapse_op<T, IN_LDS>(p, tl, op, code, instr, meas);
+    } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
+      noise_op<T, IN_LDS>(p, tl, op, code, instr, thr_lds);
+    } else {
+      clifford_op<T, IN_LDS>(p, tl, op, code);
     }
     if (code == OP_M || code == OP_MR) meas += op.n;
     __syncthreads();
   }
 }
-
-#undef FI
 
 // Detection events / observable flips: row r of `out` is the XOR of the flip
 // rows listed in idx[off[r] .. off[r+1]) (Sec. 5.6).
@@ -216,22 +342,27 @@ __global__ void __launch_bounds__(256) k_parity(const uint64_t *__restrict__ fli
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+size_t frame_lds_bytes(uint64_t n, int T, bool in_lds, uint32_t threads) {
+  return ((size_t)(threads / 64) * 64 + 64) * sizeof(uint64_t) + (in_lds ? (size_t)16 * n * T : 0);
+}
+
 template <int T, bool IN_LDS>
 static hipError_t launch_frame_t(const FrameParams &p, uint32_t tiles, uint32_t threads, size_t lds_bytes,
                                  hipStream_t stream) {
   static bool attr_set = false;
-  if (IN_LDS && !attr_set) {
+  if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)k_frame<T, IN_LDS>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_frame<T, IN_LDS>), dim3(tiles), dim3(threads), IN_LDS ? lds_bytes : 0, stream, p);
+  hipLaunchKernelGGL((k_frame<T, IN_LDS>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
   return hipGetLastError();
 }
 
 hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_t stream) {
-  size_t lds = (size_t)2 * p.num_qubits * cfg.tile_words * sizeof(uint64_t);
+  size_t lds = frame_lds_bytes(p.num_qubits, cfg.tile_words, cfg.in_lds, cfg.threads);
+  if (lds > kMaxLdsBytes || cfg.threads % 64 || cfg.threads == 0 || cfg.threads > 1024) return hipErrorInvalidValue;
   uint32_t tiles = (uint32_t)((p.num_words + cfg.tile_words - 1) / cfg.tile_words);
 #define STIM_CASE(TT)                                                                        \
   case TT:                                                                                   \

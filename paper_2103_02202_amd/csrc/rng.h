@@ -91,19 +91,32 @@ STIM_HD int gap_length(uint64_t u, const uint64_t *t) {
   return lo;
 }
 
-// Error masks of one noise site on one word.  K = 0: single mask in m[0];
+// The same G, starting from the estimate floor(log(u / 2^64) / log(1 - p))
+// (inv_log2_keep = 1 / log2(1 - p)) and then moving to the exact answer with
+// integer comparisons, so the result never depends on floating-point rounding.
+STIM_HD int gap_length_from_guess(uint64_t u, const uint64_t *t, float inv_log2_keep) {
+  float x = (float)(u >> 40) * 0x1p-24f + 0x1p-25f;      // u / 2^64, never 0
+  float est = log2f(x) * inv_log2_keep;
+  int g = est >= 64.0f ? 64 : est <= 0.0f ? 0 : (int)est;
+  while (g > 0 && u >= t[g - 1]) g--;
+  while (g < 64 && u < t[g]) g++;
+  return g;
+}
+
+// Error masks of one noise site on one word (philox(c0, c1, c2, c3, seed)
+// evaluates one generator call).  K = 0: single mask in m[0];
 // K = 3: DEPOLARIZE1, m[0] = x flips, m[1] = z flips (choice 0 X, 1 Y, 2 Z);
 // K = 15: DEPOLARIZE2, m[0..3] = x_a, z_a, x_b, z_b flips of Pauli choice + 1.
-template <int K>
-STIM_HD void noise_masks(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
-                         uint64_t v16, uint64_t m[4]) {
+template <typename Philox>
+STIM_HD void noise_masks(int K, uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
+                         float inv_log2_keep, uint64_t v16, uint64_t m[4], Philox philox) {
   // Four draws per call, kept in named registers (no indexed local array).
   uint64_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
   uint32_t j = 0;
   auto draw = [&]() -> uint64_t {
     uint32_t lane = j & 3;
     if (lane == 0) {
-      U64x4 r = philox4x64_10(instr, slot, word, (PURPOSE_NOISE_DETAIL << 32) | (j >> 2), seed, KEY_HI);
+      U64x4 r = philox(instr, slot, word, (PURPOSE_NOISE_DETAIL << 32) | (j >> 2), seed);
       b0 = r.v[0]; b1 = r.v[1]; b2 = r.v[2]; b3 = r.v[3];
     }
     j++;
@@ -112,7 +125,7 @@ STIM_HD void noise_masks(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t 
   uint64_t u = (v16 << 48) | (draw() & MASK48);
   int pos = 0;
   while (true) {
-    pos += gap_length(u, t);
+    pos += gap_length_from_guess(u, t, inv_log2_keep);
     if (pos >= 64) break;
     uint64_t bit = 1ull << pos;
     if (K == 0) {

@@ -133,8 +133,11 @@ class Circuit:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
-            stim_circuit_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.stim_circuit_free(ctypes.c_void_p(h))
+            except Exception:   # interpreter shutdown
+                pass
             self.handle = None
 
     def reference(self):
