@@ -13,6 +13,11 @@ Prints one JSON line.  Fields beyond the driver's contract:
   cpu_baseline  -- the oracle timed on this host on a bounded shot sample
   analysis_s    -- host compile + reference-sample time
   meas_mode     -- measurement-record sampling (stim_frame_sample) rate
+  batch         -- the 64-circuit mix in one persistent graph-captured launch
+                   vs the same requests one at a time
+  serving       -- Poisson request streams over the resident d = 3..101 pool:
+                   throughput and p50/p99 latency, continuous batching vs a
+                   one-at-a-time server
 """
 from __future__ import annotations
 
@@ -52,12 +57,98 @@ def cpu_baseline(text: str, num_gate_targets: int, budget_s: float = 12.0, threa
                       f"{dt:.2f} s sampling; reference sample {ref_s:.2f} s single-threaded"}
 
 
+def bench_batch(steps: int):
+    import torch
+    from paper_2103_02202_amd import serve, stim_gpu, workloads
+    mix = workloads.batch_mix(seed=0)
+    t0 = time.perf_counter()
+    pool = serve.load_pool([m["text"] for m in mix], threads=16)
+    analysis = time.perf_counter() - t0
+    reqs = []
+    sg_total = 0
+    for m, pc in zip(mix, pool):
+        c = pc.c
+        W = (m["shots"] + 63) // 64
+        if m["kind"] == "surface":
+            out0 = torch.empty((c.num_detectors, W), dtype=torch.int64, device="cuda")
+            out1 = torch.empty((max(c.num_observables, 1), W), dtype=torch.int64, device="cuda")
+            mode = 1
+        else:
+            out0 = torch.empty((c.num_measurements, W), dtype=torch.int64, device="cuda")
+            out1, mode = None, 0
+        reqs.append({"handle": c.handle, "seed": m["seed"], "shot_offset": 0, "num_shots": m["shots"],
+                     "mode": mode, "out0": out0, "out1": out1})
+        sg_total += c.num_gate_targets * m["shots"]
+    stream = torch.cuda.current_stream()
+    for _ in range(3):      # one-shot launch, then tuned + captured plan, then a replay
+        stim_gpu.stim_batch_sample(reqs, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        stim_gpu.stim_batch_sample(reqs, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    batched_ms = e0.elapsed_time(e1) / steps
+    # One circuit at a time on the same GPU, each call waited for.
+    def one_by_one():
+        for r, pc in zip(reqs, pool):
+            if r["mode"] == 1:
+                stim_gpu.stim_detector_sample(r["handle"], r["seed"], 0, r["num_shots"], r["out0"], r["out1"], stream)
+            else:
+                stim_gpu.stim_frame_sample(r["handle"], r["seed"], 0, r["num_shots"], r["out0"], stream)
+            stream.synchronize()
+    one_by_one()
+    t0 = time.perf_counter()
+    one_by_one()
+    single_ms = (time.perf_counter() - t0) * 1e3
+    return {"circuits": len(reqs), "shot_gates": sg_total, "batched_ms": batched_ms,
+            "batched_shot_gates_per_s": sg_total / (batched_ms * 1e-3), "one_at_a_time_ms": single_ms,
+            "one_at_a_time_shot_gates_per_s": sg_total / (single_ms * 1e-3),
+            "speedup_vs_one_at_a_time": single_ms / batched_ms, "analysis_s": analysis}
+
+
+def bench_serving(rates=(10, 30, 100, 300, 1000)):
+    import torch
+    from paper_2103_02202_amd import serve, workloads
+    pool_spec = workloads.serving_pool(seed=0)
+    t0 = time.perf_counter()
+    pool = serve.load_pool([x["text"] for x in pool_spec], names=[f"d{x['d']}" for x in pool_spec], threads=16)
+    analysis = time.perf_counter() - t0
+    os.environ["STIM_TUNE"] = "0"         # launches of unseen request sets are never tuned
+    # Outputs come from torch's caching allocator and the flip scratch from the
+    # library's stream-ordered pool; each can grow to the budget, so the budget
+    # is kept below half of the 288 GB of HBM.
+    srv = serve.Server(pool, hbm_budget_bytes=96 << 30, num_slots=4, max_chunk_shots=1 << 18,
+                       max_chunk_bytes=8 << 30)
+    srv.serve(workloads.serving_requests(8, rate=1000.0, pool_size=len(pool), seed=999, max_shots=4096))  # warm-up
+    out = {"pool": f"rotated surface codes d=3..101 (odd), rounds=d, p log-uniform [1e-4, 1e-2]",
+           "analysis_s": analysis, "rates": {}}
+    for rate in rates:
+        n = 50 if rate <= 10 else 100
+        reqs = workloads.serving_requests(n, rate=float(rate), pool_size=len(pool), seed=rate)
+        torch.cuda.empty_cache()
+        st = srv.serve(reqs)
+        entry = {"continuous": st}
+        if rate in (30, 300):
+            entry["one_at_a_time"] = srv.serve_one_at_a_time(
+                workloads.serving_requests(n, rate=float(rate), pool_size=len(pool), seed=rate))
+        out["rates"][str(rate)] = entry
+        print(json.dumps({"serving_rate": rate, **{k: st[k] for k in ("p50_latency_ms", "p99_latency_ms",
+                                                                       "shot_gates_per_s", "requests_per_s")}}),
+              file=sys.stderr, flush=True)
+    del os.environ["STIM_TUNE"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the shot axis shards across GPUs "
@@ -137,6 +228,10 @@ def main():
         "meas_mode": {"ms": frame_ms, "shot_gates_per_s": G * SHOTS / (frame_ms * 1e-3)},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
+    if not args.no_batch:
+        out["batch"] = bench_batch(max(3, args.steps // 2))
+    if not args.no_serving:
+        out["serving"] = bench_serving()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(text, G)
     print(json.dumps(out), flush=True)

@@ -203,6 +203,350 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   return STIM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched launches.
+// ---------------------------------------------------------------------------
+
+// Request set + device tables + captured graph, reused when the same request
+// set is submitted again.
+struct BatchPlan {
+  int device = 0;
+  std::vector<stim_request> reqs;
+  std::vector<size_t> batched, single;        // request indices inside / outside the persistent launch
+  FrameConfig cfg{1, true, 256};
+  uint64_t max_n = 0;
+  uint32_t blocks = 0, num_items = 0;
+  FrameParams *d_params = nullptr;
+  BatchItem *d_items = nullptr;
+  uint32_t *d_counter = nullptr;
+  uint64_t *d_flips = nullptr;
+  std::vector<uint64_t *> flips;              // per request (detector mode) or nullptr
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  double tuned_ms = 0;
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchPlan>> g_plans;           // most recent last
+std::map<std::string, FrameConfig> g_tuned;                // shape class -> config
+std::map<int, int> g_cu_count;
+std::vector<uint64_t> g_seen;                               // signatures of recent one-shot request sets
+
+void free_plan(BatchPlan *pl) {
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  void *ptrs[] = {pl->d_params, pl->d_items, pl->d_counter, pl->d_flips};
+  for (void *q : ptrs) if (q) (void)hipFree(q);
+}
+
+void drop_plans_using(const stim_circuit *c) {
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  for (size_t i = 0; i < g_plans.size();) {
+    bool uses = false;
+    for (const stim_request &r : g_plans[i]->reqs) uses |= r.c == c;
+    if (uses) {
+      free_plan(g_plans[i].get());
+      g_plans.erase(g_plans.begin() + (long)i);
+    } else {
+      i++;
+    }
+  }
+}
+
+bool same_request(const stim_request &a, const stim_request &b) {
+  return a.c == b.c && a.seed == b.seed && a.shot_offset == b.shot_offset && a.num_shots == b.num_shots &&
+         a.mode == b.mode && a.out0 == b.out0 && a.out1 == b.out1;
+}
+
+int cu_count(int dev) {
+  auto it = g_cu_count.find(dev);
+  if (it != g_cu_count.end()) return it->second;
+  hipDeviceProp_t prop;
+  int n = 256;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) n = prop.multiProcessorCount;
+  g_cu_count[dev] = n;
+  return n;
+}
+
+bool batch_fits(uint64_t n, int T, uint32_t threads) {
+  return frame_lds_bytes(n, T, true, threads) + kBatchStaticLds <= kMaxLdsBytes;
+}
+
+std::string shape_class(const BatchPlan &pl) {
+  uint64_t words = 0;
+  for (size_t i : pl.batched) words += (pl.reqs[i].num_shots + 63) / 64;
+  int nb = 0, wb = 0, rb = 0;
+  while ((1ull << nb) < pl.max_n) nb++;
+  while ((1ull << wb) < words) wb++;
+  while ((1ull << rb) < pl.batched.size()) rb++;
+  return std::to_string(nb) + "/" + std::to_string(wb) + "/" + std::to_string(rb);
+}
+
+hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (pl.num_items) {
+    e = launch_batch(pl.d_params, pl.d_items, pl.num_items, pl.d_counter, pl.cfg, pl.max_n, pl.blocks, s);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t i : pl.batched) {
+    const stim_request &r = pl.reqs[i];
+    if (r.mode != 1) continue;
+    DeviceCopy &d = r.c->dev[pl.device];
+    const uint64_t W = (r.num_shots + 63) / 64;
+    e = launch_parity(pl.flips[i], W, d.det_off, d.det_idx, (uint32_t)r.c->prog.num_detectors, r.out0, s);
+    if (e == hipSuccess && r.out1)
+      e = launch_parity(pl.flips[i], W, d.obs_off, d.obs_idx, (uint32_t)r.c->prog.num_observables, r.out1, s);
+    if (e != hipSuccess) return e;
+  }
+  return e;
+}
+
+// Pinned host buffers for uploading per-launch tables without blocking the
+// host: a buffer is reused only after the copy that read it has completed.
+struct StagingBuffer {
+  void *ptr = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+};
+std::vector<StagingBuffer> g_staging;
+
+int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s) {
+  StagingBuffer *buf = nullptr;
+  for (StagingBuffer &b : g_staging) {
+    if (b.busy && hipEventQuery(b.done) == hipSuccess) b.busy = false;
+    if (!b.busy && b.cap >= bytes && !buf) buf = &b;
+  }
+  if (!buf) {
+    for (StagingBuffer &b : g_staging)
+      if (!b.busy && !buf) buf = &b;
+    if (!buf) {
+      g_staging.emplace_back();
+      buf = &g_staging.back();
+      if (hipEventCreateWithFlags(&buf->done, hipEventDisableTiming) != hipSuccess)
+        return set_error(STIM_E_DEVICE, "hipEventCreate failed");
+    }
+    if (buf->cap < bytes) {
+      if (buf->ptr) (void)hipHostFree(buf->ptr);
+      buf->ptr = nullptr;
+      buf->cap = 0;
+      size_t cap = std::max<size_t>(bytes, 1 << 16);
+      if (hipHostMalloc(&buf->ptr, cap, hipHostMallocDefault) != hipSuccess)
+        return set_error(STIM_E_OOM, "pinned staging allocation failed");
+      buf->cap = cap;
+    }
+  }
+  std::memcpy(buf->ptr, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, buf->ptr, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_error(e, "table upload");
+  if ((e = hipEventRecord(buf->done, s)) != hipSuccess) return hip_error(e, "hipEventRecord");
+  buf->busy = true;
+  return STIM_OK;
+}
+
+// Kernel parameters of every request that runs inside a persistent launch.
+void batch_params(BatchPlan &pl, std::vector<FrameParams> &params, uint64_t *flips_base) {
+  uint64_t off = 0;
+  params.assign(pl.reqs.size(), FrameParams{});
+  pl.flips.assign(pl.reqs.size(), nullptr);
+  for (size_t i : pl.batched) {
+    const stim_request &r = pl.reqs[i];
+    DeviceCopy &d = r.c->dev[pl.device];
+    FrameParams &p = params[i];
+    const uint64_t W = (r.num_shots + 63) / 64;
+    p.ops = d.ops;
+    p.num_ops = (uint32_t)r.c->prog.ops.size();
+    p.num_qubits = (uint32_t)r.c->prog.num_qubits;
+    p.targets = d.targets;
+    p.thresholds = d.thresholds;
+    p.seed = r.seed;
+    p.word0 = r.shot_offset / 64;
+    p.num_words = W;
+    uint64_t rem = r.num_shots % 64;
+    p.tail_mask = rem ? ((1ull << rem) - 1) : ~0ull;
+    p.out_stride = W;
+    p.scratch = nullptr;
+    if (r.mode == 1) {
+      pl.flips[i] = flips_base + off;
+      off += std::max<uint64_t>(r.c->prog.num_measurements, 1) * W;
+      p.ref = nullptr;
+      p.out = pl.flips[i];
+    } else {
+      p.ref = d.ref;
+      p.out = r.out0;
+    }
+  }
+}
+
+// Splits requests into those that run inside the persistent launch (frames
+// fit in LDS) and the rest; returns the flip scratch size in words.
+uint64_t partition_requests(BatchPlan &pl) {
+  uint64_t total_flips = 0;
+  for (size_t i = 0; i < pl.reqs.size(); i++) {
+    const stim_request &r = pl.reqs[i];
+    if (batch_fits(r.c->prog.num_qubits, 1, 256)) {
+      pl.batched.push_back(i);
+      pl.max_n = std::max(pl.max_n, r.c->prog.num_qubits);
+      if (r.mode == 1) total_flips += std::max<uint64_t>(r.c->prog.num_measurements, 1) * ((r.num_shots + 63) / 64);
+    } else {
+      pl.single.push_back(i);
+    }
+  }
+  return total_flips;
+}
+
+std::vector<BatchItem> work_list(const BatchPlan &pl, int T) {
+  // Longest job first: tiles ordered by the work of their circuit.
+  std::vector<std::pair<uint64_t, BatchItem>> v;
+  for (size_t i : pl.batched) {
+    const stim_request &r = pl.reqs[i];
+    uint64_t W = (r.num_shots + 63) / 64, tiles = (W + T - 1) / T;
+    uint64_t cost = r.c->prog.num_gate_targets + r.c->prog.num_noise_targets + r.c->prog.num_qubits;
+    for (uint64_t t = 0; t < tiles; t++) v.push_back({cost, BatchItem{(uint32_t)i, (uint32_t)t}});
+  }
+  std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+  std::vector<BatchItem> items;
+  items.reserve(v.size());
+  for (auto &x : v) items.push_back(x.second);
+  return items;
+}
+
+FrameConfig untuned_batch_config(uint64_t max_n) {
+  for (int T : {4, 2, 1})
+    if (batch_fits(max_n, T, 256)) return FrameConfig{T, true, 256};
+  return FrameConfig{1, true, 256};
+}
+
+// One persistent launch with stream-ordered temporaries: nothing is cached and
+// nothing blocks the host.
+int run_one_shot(BatchPlan &pl, hipStream_t s) {
+  uint64_t total_flips = partition_requests(pl);
+  if (pl.batched.empty()) return STIM_OK;
+  auto known = g_tuned.find(shape_class(pl));
+  pl.cfg = known != g_tuned.end() ? known->second : untuned_batch_config(pl.max_n);
+  std::vector<BatchItem> items = work_list(pl, pl.cfg.tile_words);
+  pl.num_items = (uint32_t)items.size();
+  pl.blocks = (uint32_t)(cu_count(pl.device) * batch_blocks_per_cu(pl.cfg, pl.max_n));
+  hipError_t e;
+  if ((e = hipMallocAsync((void **)&pl.d_params, pl.reqs.size() * sizeof(FrameParams), s)) != hipSuccess ||
+      (e = hipMallocAsync((void **)&pl.d_items, std::max<size_t>(items.size(), 1) * sizeof(BatchItem), s)) !=
+          hipSuccess ||
+      (e = hipMallocAsync((void **)&pl.d_counter, sizeof(uint32_t), s)) != hipSuccess ||
+      (total_flips && (e = hipMallocAsync((void **)&pl.d_flips, total_flips * 8, s)) != hipSuccess))
+    return set_error(STIM_E_OOM, "batch allocation failed");
+  std::vector<FrameParams> params;
+  batch_params(pl, params, pl.d_flips);
+  int rc = stage_upload(params.data(), params.size() * sizeof(FrameParams), pl.d_params, s);
+  if (!rc) rc = stage_upload(items.data(), items.size() * sizeof(BatchItem), pl.d_items, s);
+  if (!rc && (e = enqueue_plan(pl, s)) != hipSuccess) rc = hip_error(e, "batch launch");
+  void *ptrs[] = {pl.d_params, pl.d_items, pl.d_counter, pl.d_flips};
+  for (void *q : ptrs) if (q) (void)hipFreeAsync(q, s);
+  pl.d_params = nullptr;
+  pl.d_items = nullptr;
+  pl.d_counter = nullptr;
+  pl.d_flips = nullptr;
+  return rc;
+}
+
+// Builds the device tables of a plan and picks its configuration: by timing
+// each candidate tile width x workgroup size on the real request set (the
+// outputs of every trial are complete and identical), unless the shape class
+// was tuned before or STIM_TUNE=0.
+int build_plan(BatchPlan &pl, hipStream_t s) {
+  hipError_t e;
+  uint64_t total_flips = partition_requests(pl);
+  if (pl.batched.empty()) return STIM_OK;
+  if (total_flips && (e = hipMalloc((void **)&pl.d_flips, total_flips * 8)) != hipSuccess)
+    return set_error(STIM_E_OOM, "batch flip scratch allocation failed");
+  std::vector<FrameParams> params;
+  batch_params(pl, params, pl.d_flips);
+  if ((e = hipMalloc((void **)&pl.d_params, params.size() * sizeof(FrameParams))) != hipSuccess ||
+      (e = hipMalloc((void **)&pl.d_counter, sizeof(uint32_t))) != hipSuccess)
+    return set_error(STIM_E_OOM, "batch table allocation failed");
+  if ((e = hipMemcpy(pl.d_params, params.data(), params.size() * sizeof(FrameParams), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_error(e, "batch table upload");
+
+  // Candidate configurations; the work list depends on the tile width.
+  std::vector<FrameConfig> cands;
+  for (int T : {1, 2, 4, 8})
+    for (uint32_t th : {256u, 512u, 1024u})
+      if (batch_fits(pl.max_n, T, th)) cands.push_back(FrameConfig{T, true, th});
+  const char *tune_env = std::getenv("STIM_TUNE");
+  const bool tune = !(tune_env && std::strcmp(tune_env, "0") == 0);
+  const std::string cls = shape_class(pl);
+  auto known = g_tuned.find(cls);
+  if (known != g_tuned.end()) cands = {known->second};
+  else if (!tune) cands = {untuned_batch_config(pl.max_n)};
+
+  BatchItem *d_items_by_T[9] = {nullptr};
+  auto items_for = [&](int T) -> BatchItem * {
+    if (d_items_by_T[T]) return d_items_by_T[T];
+    std::vector<BatchItem> items = work_list(pl, T);
+    BatchItem *d = nullptr;
+    if (hipMalloc((void **)&d, std::max<size_t>(items.size(), 1) * sizeof(BatchItem)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      return nullptr;
+    }
+    d_items_by_T[T] = d;
+    return d;
+  };
+  auto num_items_for = [&](int T) {
+    uint64_t n = 0;
+    for (size_t i : pl.batched) n += ((pl.reqs[i].num_shots + 63) / 64 + T - 1) / T;
+    return (uint32_t)n;
+  };
+  float best = 1e30f;
+  FrameConfig best_cfg = cands[0];
+  if (cands.size() > 1) {
+    hipEvent_t a, b;
+    if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess)
+      return hip_error(e, "hipEventCreate");
+    for (const FrameConfig &cfg : cands) {
+      pl.cfg = cfg;
+      pl.d_items = items_for(cfg.tile_words);
+      if (!pl.d_items) return set_error(STIM_E_OOM, "batch work list allocation failed");
+      pl.num_items = num_items_for(cfg.tile_words);
+      pl.blocks = (uint32_t)(cu_count(pl.device) * batch_blocks_per_cu(cfg, pl.max_n));
+      (void)hipEventRecord(a, s);
+      if ((e = enqueue_plan(pl, s)) != hipSuccess) return hip_error(e, "batch trial launch");
+      (void)hipEventRecord(b, s);
+      if ((e = hipEventSynchronize(b)) != hipSuccess) return hip_error(e, "batch trial");
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (ms < best) { best = ms; best_cfg = cfg; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    g_tuned[cls] = best_cfg;
+    pl.tuned_ms = best;
+  }
+  pl.cfg = best_cfg;
+  pl.d_items = items_for(best_cfg.tile_words);
+  if (!pl.d_items) return set_error(STIM_E_OOM, "batch work list allocation failed");
+  pl.num_items = num_items_for(best_cfg.tile_words);
+  pl.blocks = (uint32_t)(cu_count(pl.device) * batch_blocks_per_cu(best_cfg, pl.max_n));
+  for (int T = 1; T <= 8; T++)
+    if (d_items_by_T[T] && d_items_by_T[T] != pl.d_items) (void)hipFree(d_items_by_T[T]);
+
+  // Capture the launch sequence once; later submissions replay it.
+  hipStream_t cap;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_error(e, "stream");
+  if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return hip_error(e, "hipStreamBeginCapture");
+  }
+  hipError_t le = enqueue_plan(pl, cap);
+  e = hipStreamEndCapture(cap, &pl.graph);
+  (void)hipStreamDestroy(cap);
+  if (le != hipSuccess) return hip_error(le, "batch capture");
+  if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&pl.exec, pl.graph, nullptr, nullptr, 0)) != hipSuccess)
+    return hip_error(e, "hipGraphInstantiate");
+  return STIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -230,6 +574,7 @@ int stim_compile(const char *text, size_t len, stim_circuit **out) {
 
 void stim_circuit_free(stim_circuit *c) {
   if (!c) return;
+  drop_plans_using(c);
   int cur = 0;
   (void)hipGetDevice(&cur);
   for (auto &kv : c->dev) {
@@ -313,11 +658,84 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
 
 int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream) {
   if (!reqs && n) return set_error(STIM_E_INVALID_ARG, "null request array");
+  if (n == 0) return STIM_OK;
+  if (n > 0xFFFFFFFFull) return set_error(STIM_E_UNSUPPORTED, "too many requests");
+  hipStream_t s = (hipStream_t)hip_stream;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
   for (size_t i = 0; i < n; i++) {
     const stim_request &r = reqs[i];
+    int rc = check_sample_args(r.c, r.shot_offset, r.num_shots);
+    if (rc) return rc;
+    if (r.mode != 0 && r.mode != 1) return set_error(STIM_E_INVALID_ARG, "request mode must be 0 or 1");
+    uint64_t rows = r.mode == 0 ? r.c->prog.num_measurements : r.c->prog.num_detectors;
+    if (rows > 0 && !is_device_pointer(r.out0)) return set_error(STIM_E_INVALID_ARG, "out0 is not a device pointer");
+    if (r.mode == 1 && r.out1 && r.c->prog.num_observables > 0 && !is_device_pointer(r.out1))
+      return set_error(STIM_E_INVALID_ARG, "out1 is not a device pointer");
+    if ((r.num_shots + 63) / 64 > 0xFFFFFFFFull) return set_error(STIM_E_UNSUPPORTED, "too many shots in one request");
+    std::lock_guard<std::mutex> lock(r.c->mu);
+    DeviceCopy *d = nullptr;
+    if ((rc = ensure_reference(r.c))) return rc;
+    if ((rc = ensure_device(r.c, s, &d))) return rc;
+  }
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  BatchPlan *plan = nullptr;
+  for (size_t k = 0; k < g_plans.size() && !plan; k++) {
+    BatchPlan &pl = *g_plans[k];
+    if (pl.device != dev || pl.reqs.size() != n) continue;
+    bool same = true;
+    for (size_t i = 0; i < n && same; i++) same = same_request(pl.reqs[i], reqs[i]);
+    if (same) plan = &pl;
+  }
+  // A request set seen for the first time runs as a one-shot launch; the
+  // second submission of the same set builds a tuned, graph-captured plan.
+  uint64_t sig = 1469598103934665603ull;
+  auto mix = [&sig](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+  mix((uint64_t)dev);
+  for (size_t i = 0; i < n; i++) {
+    const stim_request &r = reqs[i];
+    mix((uint64_t)(uintptr_t)r.c); mix(r.seed); mix(r.shot_offset); mix(r.num_shots); mix((uint64_t)r.mode);
+    mix((uint64_t)(uintptr_t)r.out0); mix((uint64_t)(uintptr_t)r.out1);
+  }
+  if (!plan && std::find(g_seen.begin(), g_seen.end(), sig) == g_seen.end()) {
+    g_seen.push_back(sig);
+    if (g_seen.size() > 64) g_seen.erase(g_seen.begin());
+    BatchPlan once;
+    once.device = dev;
+    once.reqs.assign(reqs, reqs + n);
+    int rc = run_one_shot(once, s);
+    if (rc) return rc;
+    for (size_t i : once.single) {
+      const stim_request &r = once.reqs[i];
+      rc = r.mode == 0 ? stim_frame_sample(r.c, r.seed, r.shot_offset, r.num_shots, r.out0, hip_stream)
+                       : stim_detector_sample(r.c, r.seed, r.shot_offset, r.num_shots, r.out0, r.out1, hip_stream);
+      if (rc) return rc;
+    }
+    return STIM_OK;
+  }
+  if (!plan) {
+    std::unique_ptr<BatchPlan> pl(new BatchPlan());
+    pl->device = dev;
+    pl->reqs.assign(reqs, reqs + n);
+    int rc = build_plan(*pl, s);
+    if (rc) {
+      free_plan(pl.get());
+      return rc;
+    }
+    if (g_plans.size() >= 8) {
+      free_plan(g_plans.front().get());
+      g_plans.erase(g_plans.begin());
+    }
+    g_plans.push_back(std::move(pl));
+    plan = g_plans.back().get();
+  }
+  if (plan->exec && (e = hipGraphLaunch(plan->exec, s)) != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  // Requests whose frames do not fit in LDS run through the single-request path.
+  for (size_t i : plan->single) {
+    const stim_request &r = plan->reqs[i];
     int rc = r.mode == 0 ? stim_frame_sample(r.c, r.seed, r.shot_offset, r.num_shots, r.out0, hip_stream)
-             : r.mode == 1 ? stim_detector_sample(r.c, r.seed, r.shot_offset, r.num_shots, r.out0, r.out1, hip_stream)
-                           : set_error(STIM_E_INVALID_ARG, "bad request mode");
+                         : stim_detector_sample(r.c, r.seed, r.shot_offset, r.num_shots, r.out0, r.out1, hip_stream);
     if (rc) return rc;
   }
   return STIM_OK;

@@ -40,6 +40,23 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 size_t frame_lds_bytes(uint64_t n, int T, bool in_lds, uint32_t threads);
 
 hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_t stream);
+
+// One unit of work of a batched launch: tile `tile` of request `req`.
+struct BatchItem {
+  uint32_t req;
+  uint32_t tile;
+};
+
+// Static LDS of the batch kernel (the popped item index), kept out of the
+// dynamic budget.
+constexpr size_t kBatchStaticLds = 64;
+
+// Resets *counter and launches the persistent batch kernel (LDS-resident
+// frames, tile width cfg.tile_words in {1, 2, 4, 8}) over `blocks` workgroups.
+hipError_t launch_batch(const FrameParams *reqs, const BatchItem *items, uint32_t num_items, uint32_t *counter,
+                        const FrameConfig &cfg, uint64_t max_qubits, uint32_t blocks, hipStream_t stream);
+// Workgroups of the batch kernel that fit on one CU at once.
+int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits);
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,
                          uint32_t rows, uint64_t *out, hipStream_t stream);
 

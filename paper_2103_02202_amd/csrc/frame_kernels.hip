@@ -265,11 +265,11 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
   }
 }
 
+// Walks the whole program over one tile.  `lds` is the workgroup's dynamic
+// LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
 template <int T, bool IN_LDS>
-__global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
-  extern __shared__ uint64_t lds[];
+__device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, uint64_t *lds) {
   const uint32_t nwaves = blockDim.x >> 6;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t n = p.num_qubits;
   Tile<T, IN_LDS> tl;
   tl.queue = lds + (threadIdx.x >> 6) * 64;
@@ -326,6 +326,35 @@ __global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
   }
 }
 
+template <int T, bool IN_LDS>
+__global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
+  extern __shared__ uint64_t lds[];
+  walk_tile<T, IN_LDS>(p, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+// Persistent multi-circuit kernel: every workgroup pops (request, tile) items
+// from a global counter until the list is exhausted, then exits.  Frames are
+// LDS-resident; all requests of a launch share one tile width.
+template <int T>
+__global__ void __launch_bounds__(1024) k_batch(const FrameParams *__restrict__ reqs,
+                                                const BatchItem *__restrict__ items, uint32_t num_items,
+                                                uint32_t *counter) {
+  extern __shared__ uint64_t lds[];
+  __shared__ uint32_t s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    __syncthreads();
+    if (it >= num_items) break;                  // uniform: every wave leaves together
+    const BatchItem bi = items[it];
+    const FrameParams p = reqs[bi.req];
+    walk_tile<T, true>(p, bi.tile, lds);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *ptr, uint32_t value) { *ptr = value; }
+
 // Detection events / observable flips: row r of `out` is the XOR of the flip
 // rows listed in idx[off[r] .. off[r+1]) (Sec. 5.6).
 __global__ void __launch_bounds__(256) k_parity(const uint64_t *__restrict__ flips, uint64_t W,
@@ -379,6 +408,43 @@ hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_
       return hipErrorInvalidValue;
   }
 #undef STIM_CASE
+}
+
+template <int T>
+static hipError_t launch_batch_t(const FrameParams *reqs, const BatchItem *items, uint32_t num_items,
+                                 uint32_t *counter, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t stream) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kMaxLdsBytes - kBatchStaticLds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, counter, 0u);
+  hipLaunchKernelGGL((k_batch<T>), dim3(blocks), dim3(threads), lds, stream, reqs, items, num_items, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const FrameParams *reqs, const BatchItem *items, uint32_t num_items, uint32_t *counter,
+                        const FrameConfig &cfg, uint64_t max_qubits, uint32_t blocks, hipStream_t stream) {
+  size_t lds = frame_lds_bytes(max_qubits, cfg.tile_words, true, cfg.threads);
+  if (lds + kBatchStaticLds > kMaxLdsBytes || cfg.threads % 64 || cfg.threads == 0 || cfg.threads > 1024)
+    return hipErrorInvalidValue;
+  switch (cfg.tile_words) {
+    case 1: return launch_batch_t<1>(reqs, items, num_items, counter, blocks, cfg.threads, lds, stream);
+    case 2: return launch_batch_t<2>(reqs, items, num_items, counter, blocks, cfg.threads, lds, stream);
+    case 4: return launch_batch_t<4>(reqs, items, num_items, counter, blocks, cfg.threads, lds, stream);
+    case 8: return launch_batch_t<8>(reqs, items, num_items, counter, blocks, cfg.threads, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits) {
+  size_t lds = frame_lds_bytes(max_qubits, cfg.tile_words, true, cfg.threads) + kBatchStaticLds;
+  int by_lds = (int)(kMaxLdsBytes / lds);
+  int by_threads = 2048 / (int)cfg.threads;
+  int b = by_lds < by_threads ? by_lds : by_threads;
+  return b < 1 ? 1 : b;
 }
 
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,

@@ -1,0 +1,234 @@
+"""Continuous-batching sampling server over the C ABI.
+
+The server keeps a pool of compiled circuits resident on the GPU (programs and
+reference samples uploaded once) and serves detection-event sampling requests
+as they arrive:
+
+* Admission by HBM footprint: a request's device memory -- its detection-event
+  and observable outputs plus the flip record the sampler writes internally
+  (and the frame scratch when the frame is too large for LDS) -- is reserved
+  against a byte budget; requests that do not fit wait (a deferral) until
+  earlier work completes and releases memory.
+* Chunking: a request is split along the shot axis into chunks of at most
+  ``max_chunk_shots`` shots and ``max_chunk_bytes`` of footprint (results are
+  identical because random bits are keyed by absolute shot); the request
+  completes with its last chunk.
+* Continuous batching: whenever a launch slot (a HIP stream) is free, every
+  admitted chunk that has arrived is submitted together as one persistent
+  batched launch (stim_batch_sample) on that slot.  Chunks that arrive while
+  others run start on the next free slot, so their work overlaps on the
+  device.
+* Latency: arrival (the request's scheduled Poisson time) to the completion of
+  its last chunk, observed by polling HIP events; p50 / p99 reported beside
+  throughput.
+
+``Server.serve_one_at_a_time`` is the comparison point: one stream, requests in
+arrival order, each launched alone and waited for.
+"""
+from __future__ import annotations
+
+import math
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+from . import stim_gpu
+
+LDS_FRAME_LIMIT_QUBITS = 9600       # beyond this the frame slice lives in a global scratch buffer
+
+
+class PoolCircuit:
+    def __init__(self, text: str, name: str):
+        self.name = name
+        self.c = stim_gpu.Circuit(text)
+        self.c.reference()              # host analysis happens once, at pool load
+
+    def footprint(self, shots: int) -> int:
+        W = (shots + 63) // 64
+        c = self.c
+        b = 8 * W * (c.num_detectors + max(c.num_observables, 1) + max(c.num_measurements, 1))
+        if c.num_qubits > LDS_FRAME_LIMIT_QUBITS:
+            b += 16 * W * c.num_qubits
+        return b
+
+
+def load_pool(texts, names=None, threads: int = 8):
+    """Compiles circuits (and their reference samples) in parallel host threads."""
+    names = names or [str(i) for i in range(len(texts))]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda tn: PoolCircuit(*tn), zip(texts, names)))
+
+
+def percentile(values, q):
+    if not values:
+        return float("nan")
+    v = sorted(values)
+    k = (len(v) - 1) * q / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return v[lo] + (v[hi] - v[lo]) * (k - lo)
+
+
+class Server:
+    def __init__(self, pool, hbm_budget_bytes: int = 48 << 30, num_slots: int = 4,
+                 max_chunk_shots: int = 1 << 18, max_chunk_bytes: int | None = None, max_group: int = 64,
+                 max_group_shot_gates: float = 4e10, keep_outputs: bool = False):
+        import torch
+        self.torch = torch
+        self.pool = pool
+        self.budget = hbm_budget_bytes
+        self.slots = [torch.cuda.Stream() for _ in range(num_slots)]      # default priority
+        self.max_chunk = max(64, (max_chunk_shots // 64) * 64)
+        self.max_chunk_bytes = max_chunk_bytes or max(hbm_budget_bytes // 8, 1)
+        self.max_group = max_group
+        self.max_group_work = max_group_shot_gates
+        self.keep_outputs = keep_outputs
+
+    # -- chunks -------------------------------------------------------------
+    def _chunks(self, req):
+        pc = self.pool[req["circuit"]]
+        per_word = max(pc.footprint(64), 1)
+        cap = max(64, min(self.max_chunk, (self.max_chunk_bytes // per_word) * 64))
+        out = []
+        off = 0
+        while off < req["shots"]:
+            n = min(cap, req["shots"] - off)
+            out.append({"req": req, "pc": pc, "offset": off, "shots": n, "bytes": pc.footprint(n),
+                        "work": pc.c.num_gate_targets * n, "deferred": False})
+            off += n
+        return out
+
+    def _alloc(self, ch):
+        torch = self.torch
+        c = ch["pc"].c
+        W = (ch["shots"] + 63) // 64
+        ch["det"] = torch.empty((c.num_detectors, W), dtype=torch.int64, device="cuda")
+        ch["obs"] = torch.empty((max(c.num_observables, 1), W), dtype=torch.int64, device="cuda")
+
+    def _request_dict(self, ch):
+        return {"handle": ch["pc"].c.handle, "seed": ch["req"]["seed"], "shot_offset": ch["offset"],
+                "num_shots": ch["shots"], "mode": 1, "out0": ch["det"], "out1": ch["obs"]}
+
+    def _finish(self, ch, now, stats):
+        req = ch["req"]
+        req["_left"] -= 1
+        if not self.keep_outputs:
+            ch["det"] = ch["obs"] = None
+        if req["_left"] == 0:
+            req["completion"] = now
+            stats["latencies"].append(now - req["arrival"])
+
+    # -- continuous batching -----------------------------------------------
+    def serve(self, requests, time_scale: float = 1.0):
+        """Serves `requests` (dicts with arrival [s], circuit, shots, seed),
+        replaying their arrival times in real time.  Returns statistics."""
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: r["arrival"])
+        for r in reqs:
+            r["_left"] = 0
+            r["chunks"] = []
+        stats = {"latencies": [], "deferrals": 0, "launches": 0, "chunks": 0, "max_group": 0}
+        pending = []                                   # arrived, not yet admitted (FIFO)
+        inflight = []                                  # (slot index, event, chunks, bytes)
+        free_slots = list(range(len(self.slots)))
+        used = 0
+        nxt = 0
+        done = 0
+        total = len(reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < total:
+            now = time.perf_counter() - t0
+            while nxt < total and reqs[nxt]["arrival"] * time_scale <= now:
+                chs = self._chunks(reqs[nxt])
+                reqs[nxt]["_left"] = len(chs)
+                reqs[nxt]["chunks"] = chs
+                pending.extend(chs)
+                nxt += 1
+            # completions
+            still = []
+            for slot, ev, chs, nbytes in inflight:
+                if ev.query():
+                    t = time.perf_counter() - t0
+                    for ch in chs:
+                        if ch["req"]["_left"] == 1:
+                            done += 1
+                        self._finish(ch, t / time_scale if time_scale else t, stats)
+                    used -= nbytes
+                    free_slots.append(slot)
+                else:
+                    still.append((slot, ev, chs, nbytes))
+            inflight = still
+            # admissions: one group per free slot, FIFO, bounded in work so
+            # that a launch stays short and later arrivals start soon
+            while free_slots and pending:
+                group, gbytes, gwork = [], 0, 0.0
+                while (pending and len(group) < self.max_group and used + gbytes + pending[0]["bytes"] <= self.budget
+                       and (not group or gwork + pending[0]["work"] <= self.max_group_work)):
+                    ch = pending.pop(0)
+                    group.append(ch)
+                    gbytes += ch["bytes"]
+                    gwork += ch["work"]
+                if not group:
+                    if not inflight:         # a chunk larger than the whole budget: run it alone
+                        group = [pending.pop(0)]
+                        gbytes = group[0]["bytes"]
+                    else:
+                        if not pending[0]["deferred"]:
+                            pending[0]["deferred"] = True
+                            stats["deferrals"] += 1
+                        break
+                slot = free_slots.pop(0)
+                stream = self.slots[slot]
+                with torch.cuda.stream(stream):
+                    for ch in group:
+                        self._alloc(ch)
+                stim_gpu.stim_batch_sample([self._request_dict(ch) for ch in group], stream=stream)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                inflight.append((slot, ev, group, gbytes))
+                used += gbytes
+                stats["launches"] += 1
+                stats["chunks"] += len(group)
+                stats["max_group"] = max(stats["max_group"], len(group))
+            if not inflight and not pending and nxt < total:
+                wait = reqs[nxt]["arrival"] * time_scale - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.002))
+        torch.cuda.synchronize()
+        stats["makespan_s"] = time.perf_counter() - t0
+        return self._summary(reqs, stats)
+
+    # -- comparison: one request at a time ----------------------------------
+    def serve_one_at_a_time(self, requests, time_scale: float = 1.0):
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: r["arrival"])
+        stats = {"latencies": [], "deferrals": 0, "launches": 0, "chunks": 0, "max_group": 1}
+        stream = self.slots[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in reqs:
+            now = time.perf_counter() - t0
+            if r["arrival"] * time_scale > now:
+                time.sleep(r["arrival"] * time_scale - now)
+            chs = self._chunks(r)
+            r["_left"] = len(chs)
+            r["chunks"] = chs
+            for ch in chs:
+                with torch.cuda.stream(stream):
+                    self._alloc(ch)
+                    stim_gpu.stim_detector_sample(ch["pc"].c.handle, r["seed"], ch["offset"], ch["shots"],
+                                                  ch["det"], ch["obs"], stream)
+                stream.synchronize()
+                stats["launches"] += 1
+                stats["chunks"] += 1
+                self._finish(ch, time.perf_counter() - t0, stats)
+        stats["makespan_s"] = time.perf_counter() - t0
+        return self._summary(reqs, stats)
+
+    def _summary(self, reqs, stats):
+        sg = sum(self.pool[r["circuit"]].c.num_gate_targets * r["shots"] for r in reqs)
+        lat = stats["latencies"]
+        return {"requests": len(reqs), "shot_gates": sg, "makespan_s": stats["makespan_s"],
+                "shot_gates_per_s": sg / stats["makespan_s"], "requests_per_s": len(reqs) / stats["makespan_s"],
+                "p50_latency_ms": 1e3 * percentile(lat, 50), "p99_latency_ms": 1e3 * percentile(lat, 99),
+                "mean_latency_ms": 1e3 * sum(lat) / max(len(lat), 1), "deferrals": stats["deferrals"],
+                "launches": stats["launches"], "chunks": stats["chunks"], "max_group": stats["max_group"]}

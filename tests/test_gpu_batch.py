@@ -1,0 +1,132 @@
+"""Batched launches: one persistent, graph-captured launch over many circuits
+must give bit-identical results to running each request alone (and to the
+oracle), on first submission (tuned), on graph replays, and in a different
+mix."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02202_amd import workloads as wl
+from circuit_gen import random_circuit
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_2103_02202_amd import stim_gpu
+    assert torch.cuda.is_available()
+    return stim_gpu
+
+
+def make_requests(sg, specs):
+    reqs, circs = [], []
+    for text, shots, seed, mode, offset in specs:
+        c = sg.Circuit(text)
+        circs.append(c)
+        W = (shots + 63) // 64
+        if mode == 0:
+            out0 = torch.full((c.num_measurements, W), -1, dtype=torch.int64, device="cuda")
+            out1 = None
+        else:
+            out0 = torch.full((c.num_detectors, W), -1, dtype=torch.int64, device="cuda")
+            out1 = torch.full((max(c.num_observables, 1), W), -1, dtype=torch.int64, device="cuda")
+        reqs.append({"handle": c.handle, "seed": seed, "shot_offset": offset, "num_shots": shots, "mode": mode,
+                     "out0": out0, "out1": out1})
+    return reqs, circs
+
+
+def single(sg, c, r):
+    if r["mode"] == 0:
+        out = c.sample(r["seed"], r["num_shots"], shot_offset=r["shot_offset"])
+        return out, None
+    det, obs = c.detect(r["seed"], r["num_shots"], shot_offset=r["shot_offset"])
+    return det, obs
+
+
+SPECS = [
+    (wl.surface_code(3, 3, 1e-3), 1024, 0, 1, 0),
+    (wl.surface_code(5, 5, 3e-3), 5000, 1, 1, 0),
+    (wl.surface_code(7, 7, 1e-2), 777, 2, 0, 64),
+    (wl.random_clifford(64, 30, seed=3), 4096, 3, 0, 0),
+    (random_circuit(20, 150, seed=77, noise=True, p=0.05), 3333, 4, 0, 128),
+    (wl.surface_code(9, 9, 1e-4), 20000, 5, 1, 0),
+    (wl.repetition_code_example(), 2048, 6, 0, 0),
+    (wl.surface_code(25, 25, 1e-3), 3000, 7, 1, 0),
+]
+
+
+def check_against_single(sg, reqs, circs):
+    for r, c in zip(reqs, circs):
+        a, b = single(sg, c, r)
+        torch.cuda.synchronize()
+        assert torch.equal(r["out0"], a), f"request seed {r['seed']} differs from its single run"
+        if b is not None and c.num_observables:
+            assert torch.equal(r["out1"][: c.num_observables], b)
+
+
+def test_batch_matches_single_requests_and_replays(sg):
+    announce("batch mix", len(SPECS))
+    reqs, circs = make_requests(sg, SPECS)
+    sg.stim_batch_sample(reqs)
+    torch.cuda.synchronize()
+    check_against_single(sg, reqs, circs)
+    # second submission builds the tuned, graph-captured plan; the third replays it
+    for _ in range(2):
+        for r in reqs:
+            r["out0"].fill_(-1)
+        sg.stim_batch_sample(reqs)
+        torch.cuda.synchronize()
+        check_against_single(sg, reqs, circs)
+
+
+def test_batch_matches_oracle_on_small_requests(sg):
+    announce("batch vs oracle")
+    specs = [s for s in SPECS if s[1] <= 5000 and "REPEAT 24" not in s[0]][:5]
+    reqs, circs = make_requests(sg, specs)
+    sg.stim_batch_sample(reqs)
+    torch.cuda.synchronize()
+    for (text, shots, seed, mode, offset), r in zip(specs, reqs):
+        o = oracle.Circuit(text)
+        want = o.sample(seed, offset, shots, meas=mode == 0, det=mode == 1, obs=mode == 1)
+        got = r["out0"].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, want["meas" if mode == 0 else "det"])
+
+
+def test_batch_without_tuning_and_order_independence(sg, monkeypatch):
+    announce("batch untuned, reversed")
+    monkeypatch.setenv("STIM_TUNE", "0")
+    specs = list(reversed(SPECS[:6]))
+    reqs, circs = make_requests(sg, specs)
+    for _ in range(2):
+        sg.stim_batch_sample(reqs)
+        torch.cuda.synchronize()
+        check_against_single(sg, reqs, circs)
+
+
+def test_batch_generated_mix_sample(sg):
+    """A slice of the 64-circuit generated batch (shots capped for test time)."""
+    announce("generated batch mix")
+    mix = wl.batch_mix(seed=0)[::8]
+    specs = [(m["text"], min(m["shots"], 8192), m["seed"], 1 if m["kind"] == "surface" else 0, 0) for m in mix]
+    reqs, circs = make_requests(sg, specs)
+    sg.stim_batch_sample(reqs)
+    torch.cuda.synchronize()
+    check_against_single(sg, reqs, circs)
+
+
+def test_batch_rejects_bad_requests(sg):
+    announce("batch errors")
+    c = sg.Circuit("M 0\n")
+    out = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
+    with pytest.raises(sg.StimError):
+        sg.stim_batch_sample([{"handle": c.handle, "seed": 0, "shot_offset": 3, "num_shots": 64, "mode": 0,
+                               "out0": out, "out1": None}])
+    with pytest.raises(sg.StimError):
+        sg.stim_batch_sample([{"handle": c.handle, "seed": 0, "shot_offset": 0, "num_shots": 64, "mode": 7,
+                               "out0": out, "out1": None}])
