@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -37,6 +38,8 @@ struct DeviceCopy {
   uint64_t *thresholds = nullptr;
   uint64_t *ref = nullptr;
   uint32_t *det_off = nullptr, *det_idx = nullptr, *obs_off = nullptr, *obs_idx = nullptr;
+  uint32_t *noise_pc = nullptr;
+  uint64_t *noise_instr = nullptr;
 };
 
 }  // namespace
@@ -90,7 +93,9 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
       (e = upload(P.det_offsets, &d.det_off, s)) != hipSuccess ||
       (e = upload(P.det_indices, &d.det_idx, s)) != hipSuccess ||
       (e = upload(P.obs_offsets, &d.obs_off, s)) != hipSuccess ||
-      (e = upload(P.obs_indices, &d.obs_idx, s)) != hipSuccess) {
+      (e = upload(P.obs_indices, &d.obs_idx, s)) != hipSuccess ||
+      (e = upload(P.noise_pc, &d.noise_pc, s)) != hipSuccess ||
+      (e = upload(P.noise_instr, &d.noise_instr, s)) != hipSuccess) {
     return e == hipErrorOutOfMemory ? set_error(STIM_E_OOM, "device allocation failed") : hip_error(e, "upload");
   }
   // Other streams may use this copy next: make sure the upload has landed.
@@ -157,6 +162,49 @@ FrameConfig choose_config(uint64_t n, uint64_t W) {
   return cfg;
 }
 
+// Pinned host buffers for uploading per-launch tables without blocking the
+// host: a buffer is reused only after the copy that read it has completed.
+struct StagingBuffer {
+  void *ptr = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+};
+std::vector<StagingBuffer> g_staging;
+
+int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s) {
+  StagingBuffer *buf = nullptr;
+  for (StagingBuffer &b : g_staging) {
+    if (b.busy && hipEventQuery(b.done) == hipSuccess) b.busy = false;
+    if (!b.busy && b.cap >= bytes && !buf) buf = &b;
+  }
+  if (!buf) {
+    for (StagingBuffer &b : g_staging)
+      if (!b.busy && !buf) buf = &b;
+    if (!buf) {
+      g_staging.emplace_back();
+      buf = &g_staging.back();
+      if (hipEventCreateWithFlags(&buf->done, hipEventDisableTiming) != hipSuccess)
+        return set_error(STIM_E_DEVICE, "hipEventCreate failed");
+    }
+    if (buf->cap < bytes) {
+      if (buf->ptr) (void)hipHostFree(buf->ptr);
+      buf->ptr = nullptr;
+      buf->cap = 0;
+      size_t cap = std::max<size_t>(bytes, 1 << 16);
+      if (hipHostMalloc(&buf->ptr, cap, hipHostMallocDefault) != hipSuccess)
+        return set_error(STIM_E_OOM, "pinned staging allocation failed");
+      buf->cap = cap;
+    }
+  }
+  std::memcpy(buf->ptr, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, buf->ptr, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_error(e, "table upload");
+  if ((e = hipEventRecord(buf->done, s)) != hipSuccess) return hip_error(e, "hipEventRecord");
+  buf->busy = true;
+  return STIM_OK;
+}
+
 int check_sample_args(stim_circuit *c, uint64_t shot_offset, uint64_t num_shots) {
   if (!c) return set_error(STIM_E_INVALID_ARG, "null circuit handle");
   if (num_shots == 0) return set_error(STIM_E_INVALID_ARG, "num_shots must be positive");
@@ -187,8 +235,86 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   p.out_stride = W;
   p.scratch = nullptr;
   hipError_t e;
+  const uint64_t ntiles = (W + cfg.tile_words - 1) / cfg.tile_words;
+  // Noise pre-pass: reserve mean + 6 sigma + 16 records per (noise execution,
+  // tile) for the expected number of words whose prefix admits an error; ops
+  // whose reservation would exceed one workgroup's queue stay inline.
+  const Program &P = c->prog;
+  const size_t ninst = P.noise_pc.size();
+  const char *pre_env = std::getenv("STIM_NOISE_PREPASS");
+  bool prepass = ninst > 0 && !(pre_env && std::strcmp(pre_env, "0") == 0) && ntiles <= 0x7FFFFFFFull &&
+                 P.num_qubits < (1ull << 27);                    // records hold 27-bit qubit indices
+  std::vector<uint64_t> nbase(ninst);
+  std::vector<uint32_t> ncap(ninst);
+  uint64_t nrec = 0;
+  uint32_t max_cand = 64;
+  if (prepass) {
+    for (size_t i = 0; i < ninst; i++) {
+      const DevOp &op = P.ops[P.noise_pc[i]];
+      const uint32_t groups = ((op.slot0 + op.n - 1) >> 4) - (op.slot0 >> 4) + 1;
+      max_cand = std::max<uint32_t>(max_cand, groups * (uint32_t)cfg.tile_words);
+      const uint64_t cut = P.thresholds[(size_t)op.aux * 64 + 63] >> 48;
+      const double q = (65536.0 - (double)cut) / 65536.0;
+      const double mu = (double)op.n * cfg.tile_words * q;
+      double capd = std::ceil(mu + 6.0 * std::sqrt(mu) + 16.0);
+      uint32_t cap = capd > (double)kGenQueue ? 0u : (uint32_t)capd;
+      ncap[i] = cap;
+      nbase[i] = nrec;
+      nrec += (uint64_t)cap * ntiles;
+    }
+    const uint64_t kMaxRecordBytes = 8ull << 30;
+    if (nrec == 0 || nrec * 16 > kMaxRecordBytes) prepass = false;
+  }
+  uint32_t *d_counts = nullptr, *d_cap = nullptr;
+  uint64_t *d_base = nullptr;
+  uint4 *d_rec = nullptr;
+  auto free_prepass = [&]() {
+    void *ptrs[] = {d_counts, d_cap, d_base, d_rec};
+    for (void *q : ptrs) if (q) (void)hipFreeAsync(q, s);
+  };
+  if (prepass) {
+    if ((e = hipMallocAsync((void **)&d_counts, ninst * ntiles * sizeof(uint32_t), s)) != hipSuccess ||
+        (e = hipMallocAsync((void **)&d_cap, ninst * sizeof(uint32_t), s)) != hipSuccess ||
+        (e = hipMallocAsync((void **)&d_base, ninst * sizeof(uint64_t), s)) != hipSuccess ||
+        (e = hipMallocAsync((void **)&d_rec, nrec * 16, s)) != hipSuccess) {
+      free_prepass();
+      return set_error(STIM_E_OOM, "noise record allocation failed");
+    }
+    int rc = stage_upload(ncap.data(), ninst * sizeof(uint32_t), d_cap, s);
+    if (!rc) rc = stage_upload(nbase.data(), ninst * sizeof(uint64_t), d_base, s);
+    if (rc) {
+      free_prepass();
+      return rc;
+    }
+    NoiseGenParams g{};
+    g.ops = d->ops;
+    g.targets = d->targets;
+    g.thresholds = d->thresholds;
+    g.inst_pc = d->noise_pc;
+    g.inst_instr = d->noise_instr;
+    g.base = d_base;
+    g.cap = d_cap;
+    g.seed = seed;
+    g.word0 = p.word0;
+    g.num_words = W;
+    g.tiles = (uint32_t)ntiles;
+    g.counts = d_counts;
+    g.rec = d_rec;
+    // One pass over the largest op's prefix candidates per workgroup.
+    const uint32_t gen_threads = std::min<uint32_t>(512, (max_cand + 63) / 64 * 64);
+    if ((e = launch_noise_gen(g, cfg.tile_words, (uint32_t)ninst, gen_threads, s)) != hipSuccess) {
+      free_prepass();
+      return hip_error(e, "noise pre-pass launch");
+    }
+    p.noise_counts = d_counts;
+    p.noise_base = d_base;
+    p.noise_cap = d_cap;
+    p.noise_rec = d_rec;
+    p.noise_tiles = (uint32_t)ntiles;
+    p.noise_instances = (uint32_t)ninst;
+  }
   if (!cfg.in_lds) {
-    uint64_t tiles = (W + cfg.tile_words - 1) / cfg.tile_words;
+    uint64_t tiles = ntiles;
     size_t bytes = (size_t)tiles * cfg.tile_words * 16 * std::max<uint64_t>(c->prog.num_qubits, 1);
     if ((e = hipMallocAsync((void **)&p.scratch, bytes, s)) != hipSuccess)
       return set_error(STIM_E_OOM, "frame scratch allocation failed");
@@ -196,9 +322,11 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   if (c->prog.num_measurements > 0 || c->prog.num_qubits > 0) {
     if ((e = launch_frame(p, cfg, s)) != hipSuccess) {
       if (p.scratch) (void)hipFreeAsync(p.scratch, s);
+      free_prepass();
       return hip_error(e, "frame kernel launch");
     }
   }
+  free_prepass();
   if (p.scratch && (e = hipFreeAsync(p.scratch, s)) != hipSuccess) return hip_error(e, "hipFreeAsync");
   return STIM_OK;
 }
@@ -299,49 +427,6 @@ hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   return e;
-}
-
-// Pinned host buffers for uploading per-launch tables without blocking the
-// host: a buffer is reused only after the copy that read it has completed.
-struct StagingBuffer {
-  void *ptr = nullptr;
-  size_t cap = 0;
-  hipEvent_t done = nullptr;
-  bool busy = false;
-};
-std::vector<StagingBuffer> g_staging;
-
-int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s) {
-  StagingBuffer *buf = nullptr;
-  for (StagingBuffer &b : g_staging) {
-    if (b.busy && hipEventQuery(b.done) == hipSuccess) b.busy = false;
-    if (!b.busy && b.cap >= bytes && !buf) buf = &b;
-  }
-  if (!buf) {
-    for (StagingBuffer &b : g_staging)
-      if (!b.busy && !buf) buf = &b;
-    if (!buf) {
-      g_staging.emplace_back();
-      buf = &g_staging.back();
-      if (hipEventCreateWithFlags(&buf->done, hipEventDisableTiming) != hipSuccess)
-        return set_error(STIM_E_DEVICE, "hipEventCreate failed");
-    }
-    if (buf->cap < bytes) {
-      if (buf->ptr) (void)hipHostFree(buf->ptr);
-      buf->ptr = nullptr;
-      buf->cap = 0;
-      size_t cap = std::max<size_t>(bytes, 1 << 16);
-      if (hipHostMalloc(&buf->ptr, cap, hipHostMallocDefault) != hipSuccess)
-        return set_error(STIM_E_OOM, "pinned staging allocation failed");
-      buf->cap = cap;
-    }
-  }
-  std::memcpy(buf->ptr, src, bytes);
-  hipError_t e = hipMemcpyAsync(dst, buf->ptr, bytes, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_error(e, "table upload");
-  if ((e = hipEventRecord(buf->done, s)) != hipSuccess) return hip_error(e, "hipEventRecord");
-  buf->busy = true;
-  return STIM_OK;
 }
 
 // Kernel parameters of every request that runs inside a persistent launch.
@@ -580,7 +665,8 @@ void stim_circuit_free(stim_circuit *c) {
   for (auto &kv : c->dev) {
     (void)hipSetDevice(kv.first);
     DeviceCopy &d = kv.second;
-    void *ptrs[] = {d.ops, d.targets, d.thresholds, d.ref, d.det_off, d.det_idx, d.obs_off, d.obs_idx};
+    void *ptrs[] = {d.ops,     d.targets, d.thresholds, d.ref,      d.det_off,
+                    d.det_idx, d.obs_off, d.obs_idx,    d.noise_pc, d.noise_instr};
     for (void *p : ptrs) if (p) (void)hipFree(p);
   }
   if (!c->dev.empty()) (void)hipSetDevice(cur);

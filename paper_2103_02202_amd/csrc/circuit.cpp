@@ -439,6 +439,36 @@ Program compile_program(const std::vector<Node> &tree) {
     L.prog.obs_offsets.push_back((uint32_t)L.prog.obs_indices.size());
   }
   L.prog.num_observables = w.observables.size();
+  // Noise-op executions in walk order (same control flow as the kernels).
+  {
+    const size_t kMaxInstances = 65535;
+    Program &P = L.prog;
+    uint64_t flat = 0, steps = 0;
+    std::vector<uint32_t> left;
+    bool ok = true;
+    for (uint32_t pc = 0; pc < P.ops.size() && ok; pc++) {
+      if (++steps > 50000000ull) { ok = false; break; }   // very long loops: no table
+      const DevOp &op = P.ops[pc];
+      uint32_t code = op.code & 0xFFFF;
+      if (code == OP_LOOP_BEGIN) { flat += op.lead; left.push_back(op.aux); continue; }
+      if (code == OP_LOOP_END) {
+        flat += op.lead;
+        if (--left.back() > 0) pc = op.aux;
+        else left.pop_back();
+        continue;
+      }
+      uint64_t instr = 0;
+      if (code == OP_INIT) instr = ~0ull;
+      else if (op.code & OPF_NEW_INSTR) { flat += op.lead; instr = flat++; }
+      else instr = flat - 1;
+      if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
+        if (P.noise_pc.size() >= kMaxInstances) { ok = false; break; }
+        P.noise_pc.push_back(pc);
+        P.noise_instr.push_back(instr);
+      }
+    }
+    if (!ok) { P.noise_pc.clear(); P.noise_instr.clear(); }
+  }
   // Mark dead Z randomisations on init and collapse targets.
   for (const DevOp &op : L.prog.ops) {
     uint32_t code = op.code & 0xFFFF;

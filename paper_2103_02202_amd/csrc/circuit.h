@@ -80,6 +80,10 @@ struct Program {
   uint64_t num_qubits = 0, num_measurements = 0, num_detectors = 0, num_observables = 0;
   uint64_t num_gate_targets = 0, num_noise_targets = 0, num_instructions = 0;
   uint32_t max_loop_depth = 0;
+  // Every execution of a noise op in walk order: its pc and flat instruction
+  // index (empty when there are too many to tabulate).
+  std::vector<uint32_t> noise_pc;
+  std::vector<uint64_t> noise_instr;
 };
 
 struct CompileError {

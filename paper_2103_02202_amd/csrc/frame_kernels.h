@@ -23,7 +23,38 @@ struct FrameParams {
   uint64_t *out;                // [M][out_stride]
   uint64_t out_stride;
   uint64_t *scratch;            // global frame slices when not in LDS
+  // Precomputed noise (k_noise_gen), or noise_counts == NULL to draw it inline.
+  const uint32_t *noise_counts; // [noise executions][noise_tiles] record counts (kNoRecords: inline)
+  const uint64_t *noise_base;   // [noise executions] first record of tile 0
+  const uint32_t *noise_cap;    // [noise executions] records reserved per tile
+  const uint4 *noise_rec;       // 16-byte records
+  uint32_t noise_tiles;
+  uint32_t noise_instances;
 };
+
+// Record count meaning "draw this noise op inline".
+constexpr uint32_t kNoRecords = 0xFFFFFFFFu;
+// Largest record count one k_noise_gen workgroup can queue.
+constexpr uint32_t kGenQueue = 2048;
+
+struct NoiseGenParams {
+  const DevOp *ops;
+  const uint32_t *targets;
+  const uint64_t *thresholds;
+  const uint32_t *inst_pc;      // [instances] pc of each noise execution
+  const uint64_t *inst_instr;   // [instances] its flat instruction index
+  const uint64_t *base;         // [instances]
+  const uint32_t *cap;          // [instances] 0: leave to the walker
+  uint64_t seed, word0, num_words;
+  uint32_t tiles;
+  uint32_t *counts;             // [instances][tiles]
+  uint4 *rec;
+};
+
+// Fills the records of every (noise execution, tile); grid (tiles, instances),
+// `threads` (a multiple of 64, at most 1024) per workgroup.
+hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t instances, uint32_t threads,
+                            hipStream_t stream);
 
 struct FrameConfig {
   int tile_words;               // T: 1, 2, 4, 8, 16 or 32

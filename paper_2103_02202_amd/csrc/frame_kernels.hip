@@ -18,6 +18,8 @@
 // lanes together (geometric gaps, Sec. 5.5).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "circuit.h"
 #include "frame_kernels.h"
 #include "rng.h"
@@ -41,6 +43,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Barrier between ops.  With the frame in LDS only LDS traffic must be
+// visible to the other waves, so global stores (records, outputs) and
+// prefetched loads stay in flight across it; a global frame needs the full
+// fence.
+template <bool IN_LDS>
+__device__ __forceinline__ void tile_barrier() {
+  if constexpr (IN_LDS) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Exclusive prefix sum over the 64 lanes of a wave; *total gets the sum.
 __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t lane, uint32_t *total) {
   uint32_t x = v;
@@ -55,13 +72,15 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t lan
 
 template <int T, bool IN_LDS>
 struct Tile {
+  // Word index inside a plane: 32 bits suffice for an LDS-resident slice.
+  typedef typename std::conditional<IN_LDS, uint32_t, size_t>::type Index;
   uint64_t *FX, *FZ;          // frame planes
   uint64_t *queue;            // this wave's 64-entry LDS queue
   uint64_t tw0;               // first local word of the tile
   int valid;                  // words of the tile inside [0, W)
 
-  __device__ __forceinline__ size_t at(uint32_t q, int j) const {
-    if constexpr (IN_LDS) return (size_t)(q * (uint32_t)T + (uint32_t)j);
+  __device__ __forceinline__ Index at(uint32_t q, int j) const {
+    if constexpr (IN_LDS) return q * (uint32_t)T + (uint32_t)j;
     else return (size_t)q * T + j;
   }
 };
@@ -156,50 +175,66 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
 }
 
 // Collapse ops (INIT, R, M, MR): one lane per (4-slot group, word), sharing the
-// Z-randomisation call of the group.
+// Z-randomisation call of the group.  Each thread takes two groups at a time
+// and loads both groups' targets before doing either.
 template <int T, bool IN_LDS>
 __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
-                                         uint32_t code, uint64_t instr, uint64_t meas) {
+                                            uint32_t code, uint64_t instr, uint64_t meas) {
+  constexpr int V = 2;
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
   const uint32_t g_lo = s_lo >> 2, ngroups = ((s_hi - 1) >> 2) - g_lo + 1;
   const uint32_t cand = ngroups * T;
   const uint32_t *tg = p.targets + op.toff;
   const bool measures = code == OP_M || code == OP_MR;
-  for (uint32_t c = threadIdx.x; c < cand; c += blockDim.x) {
-    const uint32_t g = g_lo + c / T;
-    const int j = (int)(c % T);
-    if (j >= tl.valid) continue;
-    const uint64_t word = p.word0 + tl.tw0 + j;
-    const uint32_t sa = g * 4 < s_lo ? s_lo : g * 4, sb = g * 4 + 4 > s_hi ? s_hi : g * 4 + 4;
-    uint32_t tv[4];
-    bool need = false;
+  const uint32_t stride = blockDim.x;
+  for (uint32_t base = threadIdx.x; base < cand; base += V * stride) {
+    uint32_t tv[V][4];
+    bool ok[V];
 #pragma unroll
-    for (uint32_t u = 0; u < 4; u++) {
-      const uint32_t s = g * 4 + u;
-      tv[u] = (s >= sa && s < sb) ? tg[s - s_lo] : TGT_DEAD_ZRAND;
-      need |= !(tv[u] & TGT_DEAD_ZRAND);
-    }
-    U64x4 r{{0, 0, 0, 0}};
-    if (need) r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+    for (int v = 0; v < V; v++) {
+      const uint32_t c = base + v * stride;
+      const uint32_t g = g_lo + c / T;
+      const int j = (int)(c % T);
+      ok[v] = c < cand && j < tl.valid;
 #pragma unroll
-    for (uint32_t u = 0; u < 4; u++) {
-      const uint32_t s = g * 4 + u;
-      if (s < sa || s >= sb) continue;
-      const uint32_t k = s - s_lo, q = tv[u] & TGT_QUBIT_MASK;
-      const uint64_t zr = (tv[u] & TGT_DEAD_ZRAND) ? 0 : r.v[u];
-      const size_t ix = tl.at(q, j);
-      if (measures) {
-        const uint64_t m = meas + k;
-        uint64_t v = tl.FX[ix];
-        if (p.ref && ((p.ref[m >> 6] >> (m & 63)) & 1)) v = ~v;
-        if (tl.tw0 + j == p.num_words - 1) v &= p.tail_mask;
-        p.out[m * p.out_stride + tl.tw0 + j] = v;
+      for (uint32_t u = 0; u < 4; u++) {
+        const uint32_t s = g * 4 + u;
+        tv[v][u] = (ok[v] && s >= s_lo && s < s_hi) ? tg[s - s_lo] : (TGT_DEAD_ZRAND | 0x7FFFFFFFu);
       }
-      if (code == OP_M) {
-        tl.FZ[ix] ^= zr;
-      } else {
-        tl.FX[ix] = 0;
-        tl.FZ[ix] = zr;
+    }
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      if (!ok[v]) continue;
+      const uint32_t c = base + v * stride;
+      const uint32_t g = g_lo + c / T;
+      const int j = (int)(c % T);
+      const uint64_t word = p.word0 + tl.tw0 + j;
+      bool need = false;
+#pragma unroll
+      for (uint32_t u = 0; u < 4; u++) need |= !(tv[v][u] & TGT_DEAD_ZRAND);
+      U64x4 r{{0, 0, 0, 0}};
+      if (need) r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+#pragma unroll
+      for (uint32_t u = 0; u < 4; u++) {
+        const uint32_t s = g * 4 + u;
+        if (s < s_lo || s >= s_hi) continue;
+        const uint32_t k = s - s_lo, q = tv[v][u] & TGT_QUBIT_MASK;
+        const bool dead = (tv[v][u] & TGT_DEAD_ZRAND) != 0;
+        const uint64_t zr = dead ? 0 : r.v[u];
+        const auto ix = tl.at(q, j);
+        if (measures) {
+          const uint64_t m = meas + k;
+          uint64_t x = tl.FX[ix];
+          if (p.ref && ((p.ref[m >> 6] >> (m & 63)) & 1)) x = ~x;
+          if (tl.tw0 + j == p.num_words - 1) x &= p.tail_mask;
+          p.out[m * p.out_stride + tl.tw0 + j] = x;
+        }
+        if (code == OP_M) {
+          if (!dead) tl.FZ[ix] ^= zr;
+        } else {
+          tl.FX[ix] = 0;
+          tl.FZ[ix] = zr;
+        }
       }
     }
   }
@@ -212,14 +247,14 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
 template <int T, bool IN_LDS>
 __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                          uint32_t code) {
-  constexpr int U = 4;
+  constexpr int U = 5;
   const bool two = code == OP_CX || code == OP_CY || code == OP_CZ || code == OP_SWAP;
   const uint32_t items = op.n * T;
   const uint32_t *tg = p.targets + op.toff;
   uint64_t *FX = tl.FX, *FZ = tl.FZ;
   const uint32_t stride = blockDim.x;
   for (uint32_t base = threadIdx.x; base < items; base += U * stride) {
-    size_t ia[U], ib[U];
+    typename Tile<T, IN_LDS>::Index ia[U], ib[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -265,6 +300,147 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
   }
 }
 
+// Applies precomputed noise records: each names a qubit (and partner), a word
+// of the tile and up to five errors (6-bit position, 4-bit choice).
+template <int T, bool IN_LDS>
+__device__ __forceinline__ void apply_record(const Tile<T, IN_LDS> &tl, uint32_t code, int K, const uint4 r) {
+  {
+    const uint32_t qa = r.x & 0x7FFFFFFu, qb = r.y;
+    const int j = (int)(r.x >> 27);
+    const uint64_t h = (uint64_t)r.z | ((uint64_t)r.w << 32);
+    uint64_t mk[4] = {0, 0, 0, 0};
+    const int nh = (int)(h & 7);
+    for (int i = 0; i < nh; i++)
+      add_error(K, (int)((h >> (3 + 11 * i)) & 63), (uint32_t)((h >> (9 + 11 * i)) & 15), mk);
+    if (code == OP_NOISE_DEP2) {
+      tl.FX[tl.at(qa, j)] ^= mk[0];
+      tl.FZ[tl.at(qa, j)] ^= mk[1];
+      tl.FX[tl.at(qb, j)] ^= mk[2];
+      tl.FZ[tl.at(qb, j)] ^= mk[3];
+    } else {
+      const uint64_t mx = code == OP_NOISE_DEP1 ? mk[0] : code != OP_NOISE_Z ? mk[0] : 0;
+      const uint64_t mz = code == OP_NOISE_DEP1 ? mk[1] : code != OP_NOISE_X ? mk[0] : 0;
+      tl.FX[tl.at(qa, j)] ^= mx;
+      tl.FZ[tl.at(qa, j)] ^= mz;
+    }
+  }
+}
+
+// Records of one noise execution for this tile; the first two per thread may
+// already be in registers (loaded one op earlier).
+template <int T, bool IN_LDS>
+__device__ __forceinline__ void apply_records(const Tile<T, IN_LDS> &tl, uint32_t code, const uint4 *rec,
+                                              uint32_t count, bool have, const uint4 &r0, const uint4 &r1) {
+  const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
+  uint32_t e = threadIdx.x;
+  if (have) {
+    if (e < count) apply_record(tl, code, K, r0);
+    e += blockDim.x;
+    if (e < count) apply_record(tl, code, K, r1);
+    e += blockDim.x;
+  }
+  for (; e < count; e += blockDim.x) apply_record(tl, code, K, rec[e]);
+}
+
+// Noise pre-pass: one workgroup per (noise execution, tile).  The prefix test
+// runs over all 16-slot groups of the op; surviving (slot, word) pairs are
+// queued in LDS and expanded into records.  If the queue would exceed the
+// reserved records, or a word holds more than five errors, the count is set
+// to kNoRecords and the walker draws that op inline instead.
+template <int T>
+__global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
+  __shared__ uint64_t queue[kGenQueue];
+  __shared__ uint64_t thr[64];
+  __shared__ uint32_t s_count, s_bad;
+  const uint32_t tile = blockIdx.x, inst = blockIdx.y;
+  uint32_t *cnt = g.counts + (size_t)inst * g.tiles + tile;
+  const uint32_t cap = g.cap[inst];
+  if (cap == 0) {
+    if (threadIdx.x == 0) *cnt = kNoRecords;
+    return;
+  }
+  const DevOp op = g.ops[g.inst_pc[inst]];
+  const uint32_t code = op.code & 0xFFFFu;
+  const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
+  const uint64_t instr = g.inst_instr[inst];
+  if (threadIdx.x < 64) thr[threadIdx.x] = g.thresholds[(size_t)op.aux * 64 + threadIdx.x];
+  if (threadIdx.x == 0) { s_count = 0; s_bad = 0; }
+  __syncthreads();
+  const uint64_t cut = thr[63] >> 48;
+  const float p_est = (float)(0ull - thr[0]) * 0x1p-64f + (thr[0] == 0 ? 1.0f : 0.0f);
+  const float inv_log2_keep = 1.0f / (log1pf(-p_est) * 1.44269504088896340736f);
+  const uint64_t tw0 = (uint64_t)tile * T;
+  const int valid = (int)((g.num_words - tw0) < (uint64_t)T ? (g.num_words - tw0) : (uint64_t)T);
+  const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
+  const uint32_t g_lo = s_lo >> 4, ngroups = ((s_hi - 1) >> 4) - g_lo + 1;
+  const uint32_t cand = ngroups * T;
+  const uint32_t limit = cap < kGenQueue ? cap : kGenQueue;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t rounds = (cand + blockDim.x - 1) / blockDim.x;      // uniform
+  for (uint32_t rd = 0; rd < rounds; rd++) {
+    const uint32_t c = rd * blockDim.x + threadIdx.x;
+    const uint32_t grp = g_lo + c / T;
+    const int j = (int)(c % T);
+    uint32_t mask = 0;
+    U64x4 r{{0, 0, 0, 0}};
+    if (c < cand && j < valid) {
+      r = philox_call(instr, grp, g.word0 + tw0 + j, PURPOSE_NOISE_PREFIX << 32, g.seed);
+#pragma unroll
+      for (uint32_t b = 0; b < 16; b++) {
+        const uint32_t s = grp * 16 + b;
+        const uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
+        if (s >= s_lo && s < s_hi && v16 >= cut) mask |= 1u << b;
+      }
+    }
+    // One LDS atomic per wave: lanes take consecutive slots of the wave's range.
+    uint32_t wtotal;
+    const uint32_t wfirst = wave_exclusive_scan((uint32_t)__builtin_popcount(mask), lane, &wtotal);
+    uint32_t wbase = 0;
+    if (lane == 0 && wtotal) wbase = atomicAdd(&s_count, wtotal);
+    wbase = __shfl(wbase, 0, 64);
+    uint32_t idx = wbase + wfirst;
+    while (mask) {
+      const uint32_t b = (uint32_t)__builtin_ctz(mask);
+      mask &= mask - 1;
+      if (idx < limit) {
+        const uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
+        queue[idx] = ((uint64_t)(grp * 16 + b - s_lo) << 24) | ((uint64_t)j << 16) | v16;
+      }
+      idx++;
+    }
+  }
+  __syncthreads();
+  const uint32_t total = s_count;
+  if (total > limit) {
+    if (threadIdx.x == 0) *cnt = kNoRecords;
+    return;
+  }
+  const uint32_t *tg = g.targets + op.toff;
+  uint4 *out = g.rec + g.base[inst] + (size_t)tile * cap;
+  for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const uint64_t q = queue[e];
+    const uint32_t k = (uint32_t)(q >> 24);
+    const int j = (int)((q >> 16) & 0xFF);
+    uint64_t packed = 0;
+    int nh = 0;
+    noise_walk(K, g.seed, instr, (uint64_t)s_lo + k, g.word0 + tw0 + j, thr, inv_log2_keep, q & 0xFFFF,
+               PhiloxCall(), [&](int pos, uint32_t ch) {
+                 if (nh < 5) packed |= ((uint64_t)pos | ((uint64_t)ch << 6)) << (3 + 11 * nh);
+                 nh++;
+               });
+    if (nh > 5) s_bad = 1;
+    packed |= (uint64_t)(nh < 5 ? nh : 5);
+    uint4 rec;
+    rec.x = (code == OP_NOISE_DEP2 ? tg[2 * k] : tg[k]) | ((uint32_t)j << 27);
+    rec.y = code == OP_NOISE_DEP2 ? tg[2 * k + 1] : 0u;
+    rec.z = (uint32_t)packed;
+    rec.w = (uint32_t)(packed >> 32);
+    out[e] = rec;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *cnt = s_bad ? kNoRecords : total;
+}
+
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
 // LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
 template <int T, bool IN_LDS>
@@ -286,9 +462,27 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint64_t flat = 0, meas = 0;
   uint32_t loop_left[8];
   int depth = 0;
+  uint32_t noise_seq = 0;
+  // Two-stage prefetch of the next noise execution's records: stage A loads
+  // its count and record address (uniform), stage B -- at the start of a
+  // later op -- this thread's first two records.
+  uint32_t pf_inst = 0, pf_count = kNoRecords;
+  const uint4 *pf_rec = nullptr;
+  bool pf_a = false, pf_b = false;
+  uint4 pf_r0 = make_uint4(0, 0, 0, 0), pf_r1 = make_uint4(0, 0, 0, 0);
+  auto stage_a = [&](uint32_t inst) {
+    if (!p.noise_counts || inst >= p.noise_instances) return;
+    pf_inst = inst;
+    pf_count = p.noise_counts[(size_t)inst * p.noise_tiles + tile];
+    pf_rec = p.noise_rec + p.noise_base[inst] + (size_t)tile * p.noise_cap[inst];
+    pf_a = true;
+    pf_b = false;
+  };
+  stage_a(0);
   for (uint32_t pc = 0; pc < p.num_ops; pc++) {
     const DevOp op = p.ops[pc];
     const uint32_t code = op.code & 0xFFFFu;
+
     if (code == OP_LOOP_BEGIN) {
       flat += op.lead;
       loop_left[depth++] = op.aux;
@@ -309,20 +503,45 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     } else {
       instr = flat - 1;
     }
-    if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2 && op.aux != thr_row) {
-      thr_row = op.aux;                            // uniform: every thread takes this branch
-      if (threadIdx.x < 64) thr_lds[threadIdx.x] = p.thresholds[(size_t)thr_row * 64 + threadIdx.x];
-      __syncthreads();
-    }
     if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
       collapse_op<T, IN_LDS>(p, tl, op, code, instr, meas);
     } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
-      noise_op<T, IN_LDS>(p, tl, op, code, instr, thr_lds);
+      const uint32_t inst = noise_seq++;
+      uint32_t count = kNoRecords;                 // same value in every thread
+      const uint4 *rec = nullptr;
+      const bool have = pf_a && pf_inst == inst;
+      if (have) {
+        count = pf_count;
+        rec = pf_rec;
+      } else if (p.noise_counts && inst < p.noise_instances) {
+        count = p.noise_counts[(size_t)inst * p.noise_tiles + tile];
+        rec = p.noise_rec + p.noise_base[inst] + (size_t)tile * p.noise_cap[inst];
+      }
+      pf_a = false;
+      stage_a(inst + 1);
+      if (count != kNoRecords) {
+        apply_records<T, IN_LDS>(tl, code, rec, count, have && pf_b, pf_r0, pf_r1);
+      } else {
+        if (op.aux != thr_row) {
+          thr_row = op.aux;
+          if (threadIdx.x < 64) thr_lds[threadIdx.x] = p.thresholds[(size_t)thr_row * 64 + threadIdx.x];
+          tile_barrier<IN_LDS>();
+        }
+        noise_op<T, IN_LDS>(p, tl, op, code, instr, thr_lds);
+      }
     } else {
       clifford_op<T, IN_LDS>(p, tl, op, code);
     }
     if (code == OP_M || code == OP_MR) meas += op.n;
-    __syncthreads();
+    // Stage B of the noise prefetch, after this op's own loads have been used.
+    if (pf_a && !pf_b && !(code >= OP_NOISE_X && code <= OP_NOISE_DEP2)) {
+      if (pf_count != kNoRecords) {
+        if (threadIdx.x < pf_count) pf_r0 = pf_rec[threadIdx.x];
+        if (threadIdx.x + blockDim.x < pf_count) pf_r1 = pf_rec[threadIdx.x + blockDim.x];
+      }
+      pf_b = true;
+    }
+    tile_barrier<IN_LDS>();
   }
 }
 
@@ -343,9 +562,9 @@ __global__ void __launch_bounds__(1024) k_batch(const FrameParams *__restrict__ 
   __shared__ uint32_t s_item;
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-    __syncthreads();
+    tile_barrier<true>();
     const uint32_t it = s_item;
-    __syncthreads();
+    tile_barrier<true>();
     if (it >= num_items) break;                  // uniform: every wave leaves together
     const BatchItem bi = items[it];
     const FrameParams p = reqs[bi.req];
@@ -445,6 +664,23 @@ int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits) {
   int by_threads = 2048 / (int)cfg.threads;
   int b = by_lds < by_threads ? by_lds : by_threads;
   return b < 1 ? 1 : b;
+}
+
+hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t instances, uint32_t threads,
+                            hipStream_t stream) {
+  if (instances == 0 || g.tiles == 0) return hipSuccess;
+  if (instances > 65535 || threads == 0 || threads % 64 || threads > 1024) return hipErrorInvalidValue;
+  dim3 grid(g.tiles, instances), block(threads);
+  switch (tile_words) {
+    case 1: hipLaunchKernelGGL(k_noise_gen<1>, grid, block, 0, stream, g); break;
+    case 2: hipLaunchKernelGGL(k_noise_gen<2>, grid, block, 0, stream, g); break;
+    case 4: hipLaunchKernelGGL(k_noise_gen<4>, grid, block, 0, stream, g); break;
+    case 8: hipLaunchKernelGGL(k_noise_gen<8>, grid, block, 0, stream, g); break;
+    case 16: hipLaunchKernelGGL(k_noise_gen<16>, grid, block, 0, stream, g); break;
+    case 32: hipLaunchKernelGGL(k_noise_gen<32>, grid, block, 0, stream, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,

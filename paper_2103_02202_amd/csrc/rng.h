@@ -51,13 +51,33 @@ STIM_HD uint64_t mul_hi64(uint64_t a, uint64_t b) {
 #endif
 }
 
+// Full 64 x 64 -> 128-bit product.  On the device it is built from four
+// 32 x 32 + 64 multiply-adds (v_mad_u64_u32): the cross terms are folded into
+// the running sums so that no intermediate overflows.
+STIM_HD void mul_wide64(uint64_t m, uint64_t a, uint64_t &hi, uint64_t &lo) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t ml = (uint32_t)m, mh = (uint32_t)(m >> 32);
+  const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+  const uint64_t t0 = (uint64_t)al * ml;
+  const uint64_t t1 = (uint64_t)al * mh + (t0 >> 32);
+  const uint64_t t2 = (uint64_t)ah * ml + (uint32_t)t1;
+  hi = (uint64_t)ah * mh + (t1 >> 32) + (t2 >> 32);
+  lo = (t2 << 32) | (uint32_t)t0;
+#else
+  unsigned __int128 p = (unsigned __int128)m * a;
+  hi = (uint64_t)(p >> 64);
+  lo = (uint64_t)p;
+#endif
+}
+
 STIM_HD U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int r = 0; r < 10; r++) {
-    uint64_t lo0 = M0 * c0, hi0 = mul_hi64(M0, c0);
-    uint64_t lo1 = M1 * c2, hi1 = mul_hi64(M1, c2);
+    uint64_t lo0, hi0, lo1, hi1;
+    mul_wide64(M0, c0, hi0, lo0);
+    mul_wide64(M1, c2, hi1, lo1);
     uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     k0 += W0; k1 += W1;
@@ -103,13 +123,17 @@ STIM_HD int gap_length_from_guess(uint64_t u, const uint64_t *t, float inv_log2_
   return g;
 }
 
-// Error masks of one noise site on one word (philox(c0, c1, c2, c3, seed)
-// evaluates one generator call).  K = 0: single mask in m[0];
-// K = 3: DEPOLARIZE1, m[0] = x flips, m[1] = z flips (choice 0 X, 1 Y, 2 Z);
-// K = 15: DEPOLARIZE2, m[0..3] = x_a, z_a, x_b, z_b flips of Pauli choice + 1.
-template <typename Philox>
-STIM_HD void noise_masks(int K, uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
-                         float inv_log2_keep, uint64_t v16, uint64_t m[4], Philox philox) {
+// Walks the errors of one noise site on one word (geometric gaps, Sec. 5.5):
+// calls on_hit(position, choice) for each error in increasing position
+// (choice = floor(u K / 2^64) from the draw after the gap, K = 0: no choice).
+// philox(c0, c1, c2, c3, seed) evaluates one generator call; v16 is the
+// site's 16-bit prefix; inv_log2_keep = 1 / log2(1 - p) seeds the gap search.
+// With max_draws set, the walk stops (returning false) instead of taking draw
+// number max_draws; errors reported before that point are then incomplete.
+template <typename Philox, typename OnHit>
+STIM_HD bool noise_walk(int K, uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
+                        float inv_log2_keep, uint64_t v16, Philox philox, OnHit on_hit,
+                        uint32_t max_draws = 0xFFFFFFFFu) {
   // Four draws per call, kept in named registers (no indexed local array).
   uint64_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
   uint32_t j = 0;
@@ -127,25 +151,41 @@ STIM_HD void noise_masks(int K, uint64_t seed, uint64_t instr, uint64_t slot, ui
   while (true) {
     pos += gap_length_from_guess(u, t, inv_log2_keep);
     if (pos >= 64) break;
-    uint64_t bit = 1ull << pos;
-    if (K == 0) {
-      m[0] |= bit;
-    } else {
-      uint64_t c = mul_hi64(draw(), (uint64_t)K);
-      if (K == 3) {
-        if (c <= 1) m[0] |= bit;
-        if (c >= 1) m[1] |= bit;
-      } else {
-        uint64_t v = c + 1;
-        if (v & 1) m[0] |= bit;
-        if (v & 2) m[1] |= bit;
-        if (v & 4) m[2] |= bit;
-        if (v & 8) m[3] |= bit;
-      }
-    }
+    if (K && j >= max_draws) return false;
+    uint32_t c = K ? (uint32_t)mul_hi64(draw(), (uint64_t)K) : 0u;
+    on_hit(pos, c);
     if (++pos >= 64) break;
+    if (j >= max_draws) return false;
     u = draw();
   }
+  return true;
+}
+
+// Flip masks of one error: K = 0 single mask in m[0]; K = 3 (DEPOLARIZE1)
+// m[0] = x, m[1] = z for choice 0 X, 1 Y, 2 Z; K = 15 (DEPOLARIZE2) m[0..3] =
+// x_a, z_a, x_b, z_b from the bits of choice + 1.
+STIM_HD void add_error(int K, int pos, uint32_t c, uint64_t m[4]) {
+  uint64_t bit = 1ull << pos;
+  if (K == 0) {
+    m[0] |= bit;
+  } else if (K == 3) {
+    if (c <= 1) m[0] |= bit;
+    if (c >= 1) m[1] |= bit;
+  } else {
+    uint32_t v = c + 1;
+    if (v & 1) m[0] |= bit;
+    if (v & 2) m[1] |= bit;
+    if (v & 4) m[2] |= bit;
+    if (v & 8) m[3] |= bit;
+  }
+}
+
+// Error masks of one noise site on one word (see add_error for m).
+template <typename Philox>
+STIM_HD void noise_masks(int K, uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
+                         float inv_log2_keep, uint64_t v16, uint64_t m[4], Philox philox) {
+  noise_walk(K, seed, instr, slot, word, t, inv_log2_keep, v16, philox,
+             [&](int pos, uint32_t c) { add_error(K, pos, c, m); });
 }
 
 }  // namespace stimgpu

@@ -127,6 +127,18 @@ def test_tiling_does_not_change_results(sg, tile, placement, monkeypatch):
     check_det(sg, text, 2, 5000)
 
 
+@pytest.mark.parametrize("prepass", ["0", "1"])
+@pytest.mark.parametrize("p", [1e-4, 1e-3, 3e-2, 0.3])
+def test_noise_prepass_and_inline_agree_with_oracle(sg, prepass, p, monkeypatch):
+    """Noise drawn by the pre-pass (records) or inline in the walker; high p
+    overflows the records and falls back to the inline path per op."""
+    announce("noise path", prepass, p)
+    monkeypatch.setenv("STIM_NOISE_PREPASS", prepass)
+    text = wl.surface_code(7, 4, p)
+    check_meas(sg, text, 13, 6000)
+    check_det(sg, text, 13, 6000)
+
+
 def test_surface_d15_slices_of_full_run(sg):
     """d=15, 2^20 shots (the full configuration) on the GPU; slices checked by
     the oracle, everything checked for all-zero tails."""
