@@ -32,9 +32,14 @@ sys.path.insert(0, ROOT)
 
 D, ROUNDS, P, SHOTS, SEED = 49, 49, 1e-3, 65536, 0
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per frame-kernel launch from rocprofv3 FETCH_SIZE + WRITE_SIZE
-# (see profiles/); None until counters are taken for the current kernel.
-TRAFFIC_BYTES = None
+# HBM bytes per launch of the two kernels of one sampling pass at this
+# workload, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per
+# dispatch), scaled by what the same counters read for a plain 2 GiB device
+# copy (python bench.py --copy-probe): FETCH_SIZE reports half the bytes read,
+# WRITE_SIZE all bytes written.  None when the kernels changed after the
+# counters were taken.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+PMC_KIB = None     # {"k_noise_gen": (fetch_kib, write_kib), "k_frame": (fetch_kib, write_kib)}
 
 
 def streaming_bytes(d: int, rounds: int, p: float, shots: int) -> float:
@@ -166,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the shot axis shards across GPUs "
@@ -175,6 +182,15 @@ def main():
 
     import torch
     from paper_2103_02202_amd import stim_gpu, workloads
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
 
     text = workloads.surface_code(D, ROUNDS, P)
     t0 = time.perf_counter()
@@ -206,21 +222,30 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = G * SHOTS / (dt / args.steps)
 
-    # Frame kernel alone (measurement mode is exactly one launch of it), timed
-    # with HIP events recorded on the stream the kernel runs on.
+    # One sampling pass in measurement mode = the noise pre-pass kernel plus
+    # the frame kernel.  The pass is timed with HIP events on the stream it
+    # runs on; the library's own events split it per kernel.
     for _ in range(2):
         stim_gpu.stim_frame_sample(circ.handle, SEED, 0, SHOTS, meas, stream)
     reps = max(5, args.steps)
+    torch.cuda.synchronize()
+    stim_gpu.stim_kernel_timing(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(reps):
         stim_gpu.stim_frame_sample(circ.handle, SEED, 0, SHOTS, meas, stream)
     ev1.record(stream)
     ev1.synchronize()
-    frame_ms = ev0.elapsed_time(ev1) / reps
+    gen_ms, kframe_ms, passes = stim_gpu.stim_kernel_times()
+    stim_gpu.stim_kernel_timing(False)
+    pass_ms = ev0.elapsed_time(ev1) / reps
+    gen_ms, kframe_ms = gen_ms / passes, kframe_ms / passes
     record_bytes = M * SHOTS / 8
     alg_bytes = streaming_bytes(D, ROUNDS, P, SHOTS)
-    achieved = alg_bytes / (frame_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (pass_ms * 1e-3) / 1e9
+    traffic = None
+    if PMC_KIB:
+        traffic = sum(1024 * (f * FETCH_SCALE + w * WRITE_SCALE) for f, w in PMC_KIB.values())
 
     out = {
         "metric": "shot-gates/s + HBM GB/s frac of peak; batched/served vs single; p99 latency",
@@ -240,13 +265,17 @@ def main():
                    "shots": SHOTS, "seed": SEED, "num_qubits": circ.num_qubits, "gate_targets": G,
                    "measurements": M, "detectors": Dn},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
-                     "kernel": "k_frame (measurement mode)", "kernel_ms": frame_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "sampling pass = k_noise_gen + k_frame (measurement mode)",
+                     "pass_ms": pass_ms, "k_noise_gen_ms": gen_ms, "k_frame_ms": kframe_ms,
                      "algorithmic_bytes": alg_bytes,
-                     "algorithmic_bytes_basis": "per-op streaming (0.645 B per shot-gate at d=49)",
+                     "algorithmic_bytes_basis": f"per-op streaming, {alg_bytes / (G * SHOTS):.3f} B per shot-gate",
+                     "k_frame_frac": alg_bytes / (kframe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "measured_hbm_frac": (traffic / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
                      "compulsory_bytes": record_bytes,
-                     "compulsory_frac": record_bytes / (frame_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "meas_mode": {"ms": frame_ms, "shot_gates_per_s": G * SHOTS / (frame_ms * 1e-3)},
+                     "compulsory_frac": record_bytes / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "meas_mode": {"ms": pass_ms, "shot_gates_per_s": G * SHOTS / (pass_ms * 1e-3)},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
     if not args.no_batch:

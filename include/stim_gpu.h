@@ -116,6 +116,17 @@ typedef struct {
  * request functions one by one. */
 int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream);
 
+/* Per-kernel timing of sampling passes (stim_frame_sample and
+ * stim_detector_sample; not batched launches).  stim_kernel_timing(1) discards
+ * what was collected and starts recording HIP events on each pass's stream
+ * around its noise pre-pass kernel and its frame kernel (at most 4096 passes
+ * are kept); stim_kernel_timing(0) discards and stops.  stim_kernel_times
+ * waits for the recorded passes, writes the summed durations in milliseconds
+ * and the number of passes (any pointer may be NULL) and discards them;
+ * recording stays on.  Passes without a pre-pass add 0 to noise_gen_ms. */
+int stim_kernel_timing(int enable);
+int stim_kernel_times(double *noise_gen_ms, double *frame_ms, uint64_t *passes);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *stim_last_error(void);
 

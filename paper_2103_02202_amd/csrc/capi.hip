@@ -152,13 +152,11 @@ FrameConfig choose_config(uint64_t n, uint64_t W) {
     }
   }
   if (fits_lds(n, 1)) return cfg;
-  // Frame slice too large for LDS even for one word: global scratch.
+  // Frame slice too large for LDS even for one word: global scratch.  Two
+  // words per tile measured fastest (wider tiles leave too few workgroups).
   cfg.in_lds = false;
   cfg.threads = 256;
-  cfg.tile_words = 1;
-  for (int T : widths) {
-    if ((W + T - 1) / T >= 512) { cfg.tile_words = T; break; }
-  }
+  cfg.tile_words = W >= 1024 ? 2 : 1;
   return cfg;
 }
 
@@ -212,6 +210,25 @@ int check_sample_args(stim_circuit *c, uint64_t shot_offset, uint64_t num_shots)
   if (c->prog.max_loop_depth > 8) return set_error(STIM_E_UNSUPPORTED, "REPEAT nesting deeper than 8");
   if (c->prog.num_qubits >= (1ull << 31)) return set_error(STIM_E_UNSUPPORTED, "too many qubits");
   return STIM_OK;
+}
+
+// Optional per-kernel timing: HIP events recorded on the launch stream around
+// the noise pre-pass and the frame kernel of every sampling pass.
+struct PassEvents {
+  hipEvent_t start, mid, end;
+  bool prepass;
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<PassEvents> g_timing;
+
+void release_timing() {
+  for (PassEvents &t : g_timing) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.mid);
+    (void)hipEventDestroy(t.end);
+  }
+  g_timing.clear();
 }
 
 // Runs the frame kernel; ref == nullptr writes raw flips.
@@ -272,18 +289,44 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     void *ptrs[] = {d_counts, d_cap, d_base, d_rec};
     for (void *q : ptrs) if (q) (void)hipFreeAsync(q, s);
   };
+  PassEvents tev{};
+  bool timed = false;
+  {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    if (g_timing_on && g_timing.size() < 4096) {
+      timed = hipEventCreate(&tev.start) == hipSuccess;
+      if (timed && hipEventCreate(&tev.mid) != hipSuccess) {
+        (void)hipEventDestroy(tev.start);
+        timed = false;
+      }
+      if (timed && hipEventCreate(&tev.end) != hipSuccess) {
+        (void)hipEventDestroy(tev.start);
+        (void)hipEventDestroy(tev.mid);
+        timed = false;
+      }
+    }
+  }
+  auto drop_events = [&]() {
+    if (!timed) return;
+    (void)hipEventDestroy(tev.start);
+    (void)hipEventDestroy(tev.mid);
+    (void)hipEventDestroy(tev.end);
+    timed = false;
+  };
   if (prepass) {
     if ((e = hipMallocAsync((void **)&d_counts, ninst * ntiles * sizeof(uint32_t), s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&d_cap, ninst * sizeof(uint32_t), s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&d_base, ninst * sizeof(uint64_t), s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&d_rec, nrec * 16, s)) != hipSuccess) {
       free_prepass();
+      drop_events();
       return set_error(STIM_E_OOM, "noise record allocation failed");
     }
     int rc = stage_upload(ncap.data(), ninst * sizeof(uint32_t), d_cap, s);
     if (!rc) rc = stage_upload(nbase.data(), ninst * sizeof(uint64_t), d_base, s);
     if (rc) {
       free_prepass();
+      drop_events();
       return rc;
     }
     NoiseGenParams g{};
@@ -302,8 +345,10 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.rec = d_rec;
     // One pass over the largest op's prefix candidates per workgroup.
     const uint32_t gen_threads = std::min<uint32_t>(512, (max_cand + 63) / 64 * 64);
+    if (timed) (void)hipEventRecord(tev.start, s);
     if ((e = launch_noise_gen(g, cfg.tile_words, (uint32_t)ninst, gen_threads, s)) != hipSuccess) {
       free_prepass();
+      drop_events();
       return hip_error(e, "noise pre-pass launch");
     }
     p.noise_counts = d_counts;
@@ -316,16 +361,32 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   if (!cfg.in_lds) {
     uint64_t tiles = ntiles;
     size_t bytes = (size_t)tiles * cfg.tile_words * 16 * std::max<uint64_t>(c->prog.num_qubits, 1);
-    if ((e = hipMallocAsync((void **)&p.scratch, bytes, s)) != hipSuccess)
+    if ((e = hipMallocAsync((void **)&p.scratch, bytes, s)) != hipSuccess) {
+      free_prepass();
+      drop_events();
       return set_error(STIM_E_OOM, "frame scratch allocation failed");
+    }
   }
   if (c->prog.num_measurements > 0 || c->prog.num_qubits > 0) {
+    if (timed) {
+      if (!prepass) (void)hipEventRecord(tev.start, s);
+      (void)hipEventRecord(tev.mid, s);
+    }
     if ((e = launch_frame(p, cfg, s)) != hipSuccess) {
       if (p.scratch) (void)hipFreeAsync(p.scratch, s);
       free_prepass();
+      drop_events();
       return hip_error(e, "frame kernel launch");
     }
+    if (timed) {
+      (void)hipEventRecord(tev.end, s);
+      tev.prepass = prepass;
+      std::lock_guard<std::mutex> lock(g_timing_mu);
+      g_timing.push_back(tev);
+      timed = false;
+    }
   }
+  drop_events();
   free_prepass();
   if (p.scratch && (e = hipFreeAsync(p.scratch, s)) != hipSuccess) return hip_error(e, "hipFreeAsync");
   return STIM_OK;
@@ -740,6 +801,35 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   hipError_t fe = hipFreeAsync(flips, s);
   if (!rc && fe != hipSuccess) rc = hip_error(fe, "hipFreeAsync");
   return rc;
+}
+
+int stim_kernel_timing(int enable) {
+  std::lock_guard<std::mutex> lock(g_timing_mu);
+  release_timing();
+  g_timing_on = enable != 0;
+  return STIM_OK;
+}
+
+int stim_kernel_times(double *noise_gen_ms, double *frame_ms, uint64_t *passes) {
+  std::lock_guard<std::mutex> lock(g_timing_mu);
+  double gen = 0, frame = 0;
+  for (PassEvents &t : g_timing) {
+    hipError_t e = hipEventSynchronize(t.end);
+    float a = 0, b = 0;
+    if (e == hipSuccess && t.prepass) e = hipEventElapsedTime(&a, t.start, t.mid);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, t.mid, t.end);
+    if (e != hipSuccess) {
+      release_timing();
+      return hip_error(e, "kernel timing events");
+    }
+    gen += a;
+    frame += b;
+  }
+  if (noise_gen_ms) *noise_gen_ms = gen;
+  if (frame_ms) *frame_ms = frame;
+  if (passes) *passes = g_timing.size();
+  release_timing();
+  return STIM_OK;
 }
 
 int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream) {

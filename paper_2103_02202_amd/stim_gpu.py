@@ -47,6 +47,8 @@ def lib():
         L.stim_frame_sample.argtypes = [vp, u64, u64, u64, vp, vp]
         L.stim_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.stim_batch_sample.argtypes = [ctypes.POINTER(StimRequest), ctypes.c_size_t, vp]
+        L.stim_kernel_timing.argtypes = [ctypes.c_int]
+        L.stim_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P64]
         _lib = L
     return _lib
 
@@ -117,6 +119,17 @@ def stim_batch_sample(requests, stream=None):
         arr[i].out0 = r["out0"].data_ptr() if r.get("out0") is not None else None
         arr[i].out1 = r["out1"].data_ptr() if r.get("out1") is not None else None
     _check(lib().stim_batch_sample(arr, len(requests), _stream_ptr(stream)))
+
+
+def stim_kernel_timing(enable: bool) -> None:
+    _check(lib().stim_kernel_timing(1 if enable else 0))
+
+
+def stim_kernel_times():
+    """Returns (noise_gen_ms, frame_ms, passes) summed over the recorded passes."""
+    g, f, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64()
+    _check(lib().stim_kernel_times(ctypes.byref(g), ctypes.byref(f), ctypes.byref(n)))
+    return g.value, f.value, int(n.value)
 
 
 class Circuit:

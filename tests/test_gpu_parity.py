@@ -193,3 +193,21 @@ def test_device_pointer_validation(sg):
     rc = sg.lib().stim_frame_sample(ctypes.c_void_p(c.handle), 0, 0, 64,
                                     ctypes.c_void_p(host.ctypes.data), None)
     assert rc == sg.STIM_E_INVALID_ARG
+
+
+def test_kernel_timing_counts_passes_and_keeps_results(sg):
+    text = wl.surface_code(5, 5, 1e-2)
+    announce("kernel timing, d=5 p=1e-2 4096 shots")
+    c = sg.Circuit(text)
+    base = gpu_meas(sg, c, 3, 4096)
+    sg.stim_kernel_timing(True)
+    try:
+        timed = gpu_meas(sg, c, 3, 4096)
+        gpu_meas(sg, c, 3, 4096)
+        gen_ms, frame_ms, passes = sg.stim_kernel_times()
+        assert passes == 2
+        assert gen_ms > 0 and frame_ms > 0
+        assert sg.stim_kernel_times()[2] == 0            # read-out discards
+    finally:
+        sg.stim_kernel_timing(False)
+    assert (timed == base).all()
