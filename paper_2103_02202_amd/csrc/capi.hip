@@ -282,11 +282,12 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     const uint64_t kMaxRecordBytes = 8ull << 30;
     if (nrec == 0 || nrec * 16 > kMaxRecordBytes) prepass = false;
   }
-  uint32_t *d_counts = nullptr, *d_cap = nullptr;
+  uint2 *d_meta = nullptr;
+  uint32_t *d_cap = nullptr;
   uint64_t *d_base = nullptr;
   uint4 *d_rec = nullptr;
   auto free_prepass = [&]() {
-    void *ptrs[] = {d_counts, d_cap, d_base, d_rec};
+    void *ptrs[] = {d_meta, d_cap, d_base, d_rec};
     for (void *q : ptrs) if (q) (void)hipFreeAsync(q, s);
   };
   PassEvents tev{};
@@ -314,7 +315,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     timed = false;
   };
   if (prepass) {
-    if ((e = hipMallocAsync((void **)&d_counts, ninst * ntiles * sizeof(uint32_t), s)) != hipSuccess ||
+    if ((e = hipMallocAsync((void **)&d_meta, ninst * ntiles * sizeof(uint2), s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&d_cap, ninst * sizeof(uint32_t), s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&d_base, ninst * sizeof(uint64_t), s)) != hipSuccess ||
         (e = hipMallocAsync((void **)&d_rec, nrec * 16, s)) != hipSuccess) {
@@ -341,7 +342,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.word0 = p.word0;
     g.num_words = W;
     g.tiles = (uint32_t)ntiles;
-    g.counts = d_counts;
+    g.meta = d_meta;
     g.rec = d_rec;
     // One pass over the largest op's prefix candidates per workgroup.
     const uint32_t gen_threads = std::min<uint32_t>(512, (max_cand + 63) / 64 * 64);
@@ -351,9 +352,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
       drop_events();
       return hip_error(e, "noise pre-pass launch");
     }
-    p.noise_counts = d_counts;
-    p.noise_base = d_base;
-    p.noise_cap = d_cap;
+    p.noise_meta = d_meta;
     p.noise_rec = d_rec;
     p.noise_tiles = (uint32_t)ntiles;
     p.noise_instances = (uint32_t)ninst;

@@ -23,10 +23,10 @@ struct FrameParams {
   uint64_t *out;                // [M][out_stride]
   uint64_t out_stride;
   uint64_t *scratch;            // global frame slices when not in LDS
-  // Precomputed noise (k_noise_gen), or noise_counts == NULL to draw it inline.
-  const uint32_t *noise_counts; // [noise executions][noise_tiles] record counts (kNoRecords: inline)
-  const uint64_t *noise_base;   // [noise executions] first record of tile 0
-  const uint32_t *noise_cap;    // [noise executions] records reserved per tile
+  // Precomputed noise (k_noise_gen), or noise_meta == NULL to draw it inline.
+  // noise_meta[execution][tile] = {record count (kNoRecords: draw inline),
+  // index of the first record in noise_rec}.
+  const uint2 *noise_meta;
   const uint4 *noise_rec;       // 16-byte records
   uint32_t noise_tiles;
   uint32_t noise_instances;
@@ -47,7 +47,7 @@ struct NoiseGenParams {
   const uint32_t *cap;          // [instances] 0: leave to the walker
   uint64_t seed, word0, num_words;
   uint32_t tiles;
-  uint32_t *counts;             // [instances][tiles]
+  uint2 *meta;                  // [instances][tiles] {count, first record}
   uint4 *rec;
 };
 

@@ -70,6 +70,13 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t lan
   return x - v;
 }
 
+// Raw buffer resource over `bytes` bytes at `base`.  Buffer loads past the end
+// return zero without touching memory, so such loads can be issued
+// unconditionally (no branch around them).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 template <int T, bool IN_LDS>
 struct Tile {
   // Word index inside a plane: 32 bits suffice for an LDS-resident slice.
@@ -176,20 +183,26 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
 
 // Collapse ops (INIT, R, M, MR): one lane per (4-slot group, word), sharing the
 // Z-randomisation call of the group.  Each thread takes two groups at a time
-// and loads both groups' targets before doing either.
-template <int T, bool IN_LDS>
+// and loads both groups' targets (and reference words) before doing either.
+// Every thread runs at least one pass, and every load of a pass is issued
+// unconditionally (clamped indices), then `after_loads` runs: loads complete in issue order, so the loads it
+// issues stay in flight while the pass waits only for its own.
+template <int T, bool IN_LDS, typename AfterLoads>
 __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
-                                            uint32_t code, uint64_t instr, uint64_t meas) {
+                                            uint32_t code, uint64_t instr, uint64_t meas, AfterLoads after_loads) {
   constexpr int V = 2;
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
   const uint32_t g_lo = s_lo >> 2, ngroups = ((s_hi - 1) >> 2) - g_lo + 1;
   const uint32_t cand = ngroups * T;
   const uint32_t *tg = p.targets + op.toff;
   const bool measures = code == OP_M || code == OP_MR;
+  const bool use_ref = measures && p.ref != nullptr;
   const uint32_t stride = blockDim.x;
-  for (uint32_t base = threadIdx.x; base < cand; base += V * stride) {
+  uint32_t base = threadIdx.x;
+  do {
     uint32_t tv[V][4];
     bool ok[V];
+    uint64_t rw[V][2];           // reference words of the group's measurements
 #pragma unroll
     for (int v = 0; v < V; v++) {
       const uint32_t c = base + v * stride;
@@ -199,9 +212,19 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
 #pragma unroll
       for (uint32_t u = 0; u < 4; u++) {
         const uint32_t s = g * 4 + u;
-        tv[v][u] = (ok[v] && s >= s_lo && s < s_hi) ? tg[s - s_lo] : (TGT_DEAD_ZRAND | 0x7FFFFFFFu);
+        const bool in = ok[v] && s >= s_lo && s < s_hi;
+        const uint32_t t = tg[in ? s - s_lo : 0];
+        tv[v][u] = in ? t : (TGT_DEAD_ZRAND | 0x7FFFFFFFu);
+      }
+      rw[v][0] = rw[v][1] = 0;
+      if (use_ref) {             // uniform; the loads after it are issued on both paths
+        const uint64_t m0 = meas + ((g * 4 > s_lo ? g * 4 : s_lo) - s_lo);
+        const uint64_t m1 = meas + ((g * 4 + 3 < s_hi - 1 ? g * 4 + 3 : s_hi - 1) - s_lo);
+        rw[v][0] = p.ref[ok[v] ? m0 >> 6 : 0];
+        rw[v][1] = p.ref[ok[v] ? m1 >> 6 : 0];
       }
     }
+    after_loads();
 #pragma unroll
     for (int v = 0; v < V; v++) {
       if (!ok[v]) continue;
@@ -214,6 +237,7 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
       for (uint32_t u = 0; u < 4; u++) need |= !(tv[v][u] & TGT_DEAD_ZRAND);
       U64x4 r{{0, 0, 0, 0}};
       if (need) r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+      const uint64_t m0 = meas + ((g * 4 > s_lo ? g * 4 : s_lo) - s_lo);
 #pragma unroll
       for (uint32_t u = 0; u < 4; u++) {
         const uint32_t s = g * 4 + u;
@@ -225,7 +249,8 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
         if (measures) {
           const uint64_t m = meas + k;
           uint64_t x = tl.FX[ix];
-          if (p.ref && ((p.ref[m >> 6] >> (m & 63)) & 1)) x = ~x;
+          const uint64_t refw = (m >> 6) == (m0 >> 6) ? rw[v][0] : rw[v][1];
+          if (use_ref && ((refw >> (m & 63)) & 1)) x = ~x;
           if (tl.tw0 + j == p.num_words - 1) x &= p.tail_mask;
           p.out[m * p.out_stride + tl.tw0 + j] = x;
         }
@@ -237,23 +262,25 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
         }
       }
     }
-  }
+    base += V * stride;
+  } while (base < cand);
 }
 
 // Clifford ops: one item per (target, word).  A thread takes up to U items at
 // once and issues all of their target loads and frame reads before any write;
 // the items of one op touch distinct (qubit, word) cells, so this is safe and
-// hides the load latency.
-template <int T, bool IN_LDS>
+// hides the load latency.  Passes and `after_loads` as for collapse ops.
+template <int T, bool IN_LDS, typename AfterLoads>
 __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
-                                         uint32_t code) {
+                                         uint32_t code, AfterLoads after_loads) {
   constexpr int U = 5;
   const bool two = code == OP_CX || code == OP_CY || code == OP_CZ || code == OP_SWAP;
   const uint32_t items = op.n * T;
   const uint32_t *tg = p.targets + op.toff;
   uint64_t *FX = tl.FX, *FZ = tl.FZ;
   const uint32_t stride = blockDim.x;
-  for (uint32_t base = threadIdx.x; base < items; base += U * stride) {
+  uint32_t base = threadIdx.x;
+  do {
     typename Tile<T, IN_LDS>::Index ia[U], ib[U];
     bool ok[U];
 #pragma unroll
@@ -262,14 +289,13 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
       const uint32_t k = it / T;
       const int j = (int)(it % T);
       ok[u] = it < items && j < tl.valid;
-      uint32_t qa = 0, qb = 0;
-      if (ok[u]) {
-        qa = tg[two ? 2 * k : k];
-        if (two) qb = tg[2 * k + 1];
-      }
+      const uint32_t kk = ok[u] ? k : 0;
+      const uint32_t qa = tg[two ? 2 * kk : kk];
+      const uint32_t qb = tg[two ? 2 * kk + 1 : kk];
       ia[u] = tl.at(qa, j);
       ib[u] = tl.at(qb, j);
     }
+    after_loads();
     uint64_t xa[U], za[U], xb[U], zb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -297,7 +323,8 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
           break;
       }
     }
-  }
+    base += U * stride;
+  } while (base < items);
 }
 
 // Applies precomputed noise records: each names a qubit (and partner), a word
@@ -353,10 +380,11 @@ __global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
   __shared__ uint64_t thr[64];
   __shared__ uint32_t s_count, s_bad;
   const uint32_t tile = blockIdx.x, inst = blockIdx.y;
-  uint32_t *cnt = g.counts + (size_t)inst * g.tiles + tile;
+  uint2 *meta = g.meta + (size_t)inst * g.tiles + tile;
   const uint32_t cap = g.cap[inst];
+  const uint32_t first = (uint32_t)(g.base[inst] + (uint64_t)tile * cap);
   if (cap == 0) {
-    if (threadIdx.x == 0) *cnt = kNoRecords;
+    if (threadIdx.x == 0) *meta = make_uint2(kNoRecords, 0u);
     return;
   }
   const DevOp op = g.ops[g.inst_pc[inst]];
@@ -412,11 +440,11 @@ __global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
   __syncthreads();
   const uint32_t total = s_count;
   if (total > limit) {
-    if (threadIdx.x == 0) *cnt = kNoRecords;
+    if (threadIdx.x == 0) *meta = make_uint2(kNoRecords, 0u);
     return;
   }
   const uint32_t *tg = g.targets + op.toff;
-  uint4 *out = g.rec + g.base[inst] + (size_t)tile * cap;
+  uint4 *out = g.rec + first;
   for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
     const uint64_t q = queue[e];
     const uint32_t k = (uint32_t)(q >> 24);
@@ -438,7 +466,7 @@ __global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
     out[e] = rec;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *cnt = s_bad ? kNoRecords : total;
+  if (threadIdx.x == 0) *meta = make_uint2(s_bad ? kNoRecords : total, first);
 }
 
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
@@ -463,20 +491,37 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint32_t loop_left[8];
   int depth = 0;
   uint32_t noise_seq = 0;
-  // Two-stage prefetch of the next noise execution's records: stage A loads
-  // its count and record address (uniform), stage B -- at the start of a
-  // later op -- this thread's first two records.
-  uint32_t pf_inst = 0, pf_count = kNoRecords;
-  const uint4 *pf_rec = nullptr;
-  bool pf_a = false, pf_b = false;
-  uint4 pf_r0 = make_uint4(0, 0, 0, 0), pf_r1 = make_uint4(0, 0, 0, 0);
+  // Two-stage prefetch of the next noise execution's records.  Stage A (at a
+  // noise op) loads the next execution's {count, first record}; stage B (in
+  // each following op, right after that op's own loads) loads this thread's
+  // first two records.  Both are vector loads issued on every path: scalar
+  // loads would share their wait counter with LDS traffic, and a load issued
+  // on one path only makes later waits conservative.
+  const bool recs = p.noise_meta != nullptr;
+  uint32_t a_inst = 0;
+  uint2 a_meta = make_uint2(kNoRecords, 0u);
   auto stage_a = [&](uint32_t inst) {
-    if (!p.noise_counts || inst >= p.noise_instances) return;
-    pf_inst = inst;
-    pf_count = p.noise_counts[(size_t)inst * p.noise_tiles + tile];
-    pf_rec = p.noise_rec + p.noise_base[inst] + (size_t)tile * p.noise_cap[inst];
-    pf_a = true;
-    pf_b = false;
+    const bool ok = recs && inst < p.noise_instances;
+    const uint2 *src = p.noise_meta + (ok ? (size_t)inst * p.noise_tiles + tile : 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(buffer_rsrc(src, ok ? 8u : 0u), 0, 0, 0);
+    a_meta = make_uint2(v[0], v[1]);
+    a_inst = ok ? inst : 0xFFFFFFFFu;
+  };
+  uint32_t pf_inst = 0xFFFFFFFFu, pf_count = kNoRecords;
+  const uint4 *pf_rec = p.noise_rec;
+  uint4 pf_r0 = make_uint4(0, 0, 0, 0), pf_r1 = make_uint4(0, 0, 0, 0);
+  auto stage_b = [&]() {
+    const uint32_t count = __builtin_amdgcn_readfirstlane(a_meta.x);
+    const uint32_t first = __builtin_amdgcn_readfirstlane(a_meta.y);
+    const bool ok = a_inst != 0xFFFFFFFFu && count != kNoRecords;
+    pf_inst = a_inst;
+    pf_count = ok ? count : kNoRecords;
+    pf_rec = p.noise_rec + (ok ? first : 0u);
+    const auto rs = buffer_rsrc(pf_rec, ok ? count * 16u : 0u);
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, threadIdx.x * 16u, 0, 0);
+    const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (threadIdx.x + blockDim.x) * 16u, 0, 0);
+    pf_r0 = make_uint4(v0[0], v0[1], v0[2], v0[3]);
+    pf_r1 = make_uint4(v1[0], v1[1], v1[2], v1[3]);
   };
   stage_a(0);
   for (uint32_t pc = 0; pc < p.num_ops; pc++) {
@@ -504,23 +549,24 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       instr = flat - 1;
     }
     if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
-      collapse_op<T, IN_LDS>(p, tl, op, code, instr, meas);
+      collapse_op<T, IN_LDS>(p, tl, op, code, instr, meas, stage_b);
     } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
       const uint32_t inst = noise_seq++;
       uint32_t count = kNoRecords;                 // same value in every thread
-      const uint4 *rec = nullptr;
-      const bool have = pf_a && pf_inst == inst;
-      if (have) {
+      const uint4 *rec = p.noise_rec;
+      bool have = false;
+      if (pf_inst == inst) {                       // records already in flight
         count = pf_count;
         rec = pf_rec;
-      } else if (p.noise_counts && inst < p.noise_instances) {
-        count = p.noise_counts[(size_t)inst * p.noise_tiles + tile];
-        rec = p.noise_rec + p.noise_base[inst] + (size_t)tile * p.noise_cap[inst];
+        have = true;
+      } else if (a_inst == inst) {                 // e.g. two noise ops in a row
+        count = __builtin_amdgcn_readfirstlane(a_meta.x);
+        rec = p.noise_rec + __builtin_amdgcn_readfirstlane(a_meta.y);
       }
-      pf_a = false;
+      pf_inst = 0xFFFFFFFFu;
       stage_a(inst + 1);
       if (count != kNoRecords) {
-        apply_records<T, IN_LDS>(tl, code, rec, count, have && pf_b, pf_r0, pf_r1);
+        apply_records<T, IN_LDS>(tl, code, rec, count, have, pf_r0, pf_r1);
       } else {
         if (op.aux != thr_row) {
           thr_row = op.aux;
@@ -530,17 +576,9 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
         noise_op<T, IN_LDS>(p, tl, op, code, instr, thr_lds);
       }
     } else {
-      clifford_op<T, IN_LDS>(p, tl, op, code);
+      clifford_op<T, IN_LDS>(p, tl, op, code, stage_b);
     }
     if (code == OP_M || code == OP_MR) meas += op.n;
-    // Stage B of the noise prefetch, after this op's own loads have been used.
-    if (pf_a && !pf_b && !(code >= OP_NOISE_X && code <= OP_NOISE_DEP2)) {
-      if (pf_count != kNoRecords) {
-        if (threadIdx.x < pf_count) pf_r0 = pf_rec[threadIdx.x];
-        if (threadIdx.x + blockDim.x < pf_count) pf_r1 = pf_rec[threadIdx.x + blockDim.x];
-      }
-      pf_b = true;
-    }
     tile_barrier<IN_LDS>();
   }
 }
