@@ -266,19 +266,29 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
   } while (base < cand);
 }
 
-// Clifford ops: one item per (target, word).  A thread takes up to U items at
-// once and issues all of their target loads and frame reads before any write;
-// the items of one op touch distinct (qubit, word) cells, so this is safe and
-// hides the load latency.  Passes and `after_loads` as for collapse ops.
+// Clifford ops: one item per (target, pair of words) -- a thread moves two
+// adjacent words of a qubit with one 16-byte LDS access (one word when T = 1).
+// A thread takes up to U items at once and issues all of their target loads
+// and frame reads before any write; the items of one op touch distinct
+// (qubit, word) cells, so this is safe and hides the load latency.  Words of
+// the tile past the end of the shot range are updated too (they belong to no
+// shot and are never written out).  Every thread runs at least one pass, and
+// every load of a pass is issued unconditionally (clamped indices), so that
+// the compiler can wait for exactly the loads it needs.
 template <int T, bool IN_LDS, typename AfterLoads>
 __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                          uint32_t code, AfterLoads after_loads) {
-  constexpr int U = 5;
+  constexpr int U = 3;
+  constexpr uint32_t C = T >= 2 ? 2 : 1;          // words per item
+  constexpr uint32_t CPT = T / C;                 // items per target
+  typedef uint64_t U64x2v __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<C == 2, U64x2v, uint64_t>::type Vec;
   const bool two = code == OP_CX || code == OP_CY || code == OP_CZ || code == OP_SWAP;
-  const uint32_t items = op.n * T;
+  const uint32_t items = op.n * CPT;
   const uint32_t *tg = p.targets + op.toff;
-  uint64_t *FX = tl.FX, *FZ = tl.FZ;
   const uint32_t stride = blockDim.x;
+  auto X = [&](typename Tile<T, IN_LDS>::Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FX + i); };
+  auto Z = [&](typename Tile<T, IN_LDS>::Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FZ + i); };
   uint32_t base = threadIdx.x;
   do {
     typename Tile<T, IN_LDS>::Index ia[U], ib[U];
@@ -286,40 +296,43 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const uint32_t it = base + u * stride;
-      const uint32_t k = it / T;
-      const int j = (int)(it % T);
-      ok[u] = it < items && j < tl.valid;
+      const uint32_t k = it / CPT;
+      const int j = (int)((it % CPT) * C);
+      ok[u] = it < items;
       const uint32_t kk = ok[u] ? k : 0;
       const uint32_t qa = tg[two ? 2 * kk : kk];
-      const uint32_t qb = tg[two ? 2 * kk + 1 : kk];
+      const uint32_t qb = two ? tg[2 * kk + 1] : qa;
       ia[u] = tl.at(qa, j);
       ib[u] = tl.at(qb, j);
     }
     after_loads();
-    uint64_t xa[U], za[U], xb[U], zb[U];
+    Vec xa[U], za[U], xb[U], zb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      xa[u] = ok[u] ? FX[ia[u]] : 0;
-      za[u] = ok[u] ? FZ[ia[u]] : 0;
-      xb[u] = ok[u] && two ? FX[ib[u]] : 0;
-      zb[u] = ok[u] && two ? FZ[ib[u]] : 0;
+      if (!ok[u]) continue;
+      xa[u] = X(ia[u]);
+      za[u] = Z(ia[u]);
+      if (two) {
+        xb[u] = X(ib[u]);
+        zb[u] = Z(ib[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
       if (!ok[u]) continue;
       switch (code) {
-        case OP_SWAP_XZ: FX[ia[u]] = za[u]; FZ[ia[u]] = xa[u]; break;
-        case OP_Z_XOR_X: FZ[ia[u]] = za[u] ^ xa[u]; break;
-        case OP_X_XOR_Z: FX[ia[u]] = xa[u] ^ za[u]; break;
-        case OP_CX: FX[ib[u]] = xb[u] ^ xa[u]; FZ[ia[u]] = za[u] ^ zb[u]; break;
-        case OP_CZ: FZ[ia[u]] = za[u] ^ xb[u]; FZ[ib[u]] = zb[u] ^ xa[u]; break;
+        case OP_SWAP_XZ: X(ia[u]) = za[u]; Z(ia[u]) = xa[u]; break;
+        case OP_Z_XOR_X: Z(ia[u]) = za[u] ^ xa[u]; break;
+        case OP_X_XOR_Z: X(ia[u]) = xa[u] ^ za[u]; break;
+        case OP_CX: X(ib[u]) = xb[u] ^ xa[u]; Z(ia[u]) = za[u] ^ zb[u]; break;
+        case OP_CZ: Z(ia[u]) = za[u] ^ xb[u]; Z(ib[u]) = zb[u] ^ xa[u]; break;
         case OP_CY:
-          FX[ib[u]] = xb[u] ^ xa[u];
-          FZ[ib[u]] = zb[u] ^ xa[u];
-          FZ[ia[u]] = za[u] ^ xb[u] ^ zb[u];
+          X(ib[u]) = xb[u] ^ xa[u];
+          Z(ib[u]) = zb[u] ^ xa[u];
+          Z(ia[u]) = za[u] ^ xb[u] ^ zb[u];
           break;
         default:   // SWAP
-          FX[ia[u]] = xb[u]; FZ[ia[u]] = zb[u]; FX[ib[u]] = xa[u]; FZ[ib[u]] = za[u];
+          X(ia[u]) = xb[u]; Z(ia[u]) = zb[u]; X(ib[u]) = xa[u]; Z(ib[u]) = za[u];
           break;
       }
     }
