@@ -261,21 +261,22 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   const char *pre_env = std::getenv("STIM_NOISE_PREPASS");
   bool prepass = ninst > 0 && !(pre_env && std::strcmp(pre_env, "0") == 0) && ntiles <= 0x7FFFFFFFull &&
                  P.num_qubits < (1ull << 27);                    // records hold 27-bit qubit indices
+  // Reservations above this many records per (execution, tile) stay inline.
+  const uint32_t kMaxTileRecords = kGenQueue / 2;
   std::vector<uint64_t> nbase(ninst);
   std::vector<uint32_t> ncap(ninst);
   uint64_t nrec = 0;
-  uint32_t max_cand = 64;
+  uint32_t max_cap = 1;
   if (prepass) {
     for (size_t i = 0; i < ninst; i++) {
       const DevOp &op = P.ops[P.noise_pc[i]];
-      const uint32_t groups = ((op.slot0 + op.n - 1) >> 4) - (op.slot0 >> 4) + 1;
-      max_cand = std::max<uint32_t>(max_cand, groups * (uint32_t)cfg.tile_words);
       const uint64_t cut = P.thresholds[(size_t)op.aux * 64 + 63] >> 48;
       const double q = (65536.0 - (double)cut) / 65536.0;
       const double mu = (double)op.n * cfg.tile_words * q;
       double capd = std::ceil(mu + 6.0 * std::sqrt(mu) + 16.0);
-      uint32_t cap = capd > (double)kGenQueue ? 0u : (uint32_t)capd;
+      uint32_t cap = capd > (double)kMaxTileRecords ? 0u : (uint32_t)capd;
       ncap[i] = cap;
+      max_cap = std::max(max_cap, cap);
       nbase[i] = nrec;
       nrec += (uint64_t)cap * ntiles;
     }
@@ -344,8 +345,11 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.tiles = (uint32_t)ntiles;
     g.meta = d_meta;
     g.rec = d_rec;
-    // One pass over the largest op's prefix candidates per workgroup.
-    const uint32_t gen_threads = std::min<uint32_t>(512, (max_cand + 63) / 64 * 64);
+    // Each workgroup takes as many tiles of one execution as its LDS queue
+    // holds at the largest reservation, so that its lanes stay busy.
+    g.tiles_per_group = std::max<uint32_t>(1, std::min<uint32_t>(kGenTiles, kGenQueue / max_cap));
+    g.queue_per_tile = kGenQueue / g.tiles_per_group;
+    const uint32_t gen_threads = 256;
     if (timed) (void)hipEventRecord(tev.start, s);
     if ((e = launch_noise_gen(g, cfg.tile_words, (uint32_t)ninst, gen_threads, s)) != hipSuccess) {
       free_prepass();

@@ -34,8 +34,10 @@ struct FrameParams {
 
 // Record count meaning "draw this noise op inline".
 constexpr uint32_t kNoRecords = 0xFFFFFFFFu;
-// Largest record count one k_noise_gen workgroup can queue.
-constexpr uint32_t kGenQueue = 2048;
+// LDS queue entries of one k_noise_gen workgroup (shared by its tiles), and
+// the most tiles one workgroup takes.
+constexpr uint32_t kGenQueue = 4096;
+constexpr uint32_t kGenTiles = 8;
 
 struct NoiseGenParams {
   const DevOp *ops;
@@ -47,12 +49,14 @@ struct NoiseGenParams {
   const uint32_t *cap;          // [instances] 0: leave to the walker
   uint64_t seed, word0, num_words;
   uint32_t tiles;
+  uint32_t tiles_per_group;     // tiles per workgroup (at most kGenTiles)
+  uint32_t queue_per_tile;      // LDS queue entries per tile (tiles_per_group * this <= kGenQueue)
   uint2 *meta;                  // [instances][tiles] {count, first record}
   uint4 *rec;
 };
 
-// Fills the records of every (noise execution, tile); grid (tiles, instances),
-// `threads` (a multiple of 64, at most 1024) per workgroup.
+// Fills the records of every (noise execution, tile); grid (tile groups,
+// instances), `threads` (a multiple of 64, at most 512) per workgroup.
 hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t instances, uint32_t threads,
                             hipStream_t stream);
 

@@ -382,22 +382,27 @@ __device__ __forceinline__ void apply_records(const Tile<T, IN_LDS> &tl, uint32_
   for (; e < count; e += blockDim.x) apply_record(tl, code, K, rec[e]);
 }
 
-// Noise pre-pass: one workgroup per (noise execution, tile).  The prefix test
-// runs over all 16-slot groups of the op; surviving (slot, word) pairs are
-// queued in LDS and expanded into records.  If the queue would exceed the
-// reserved records, or a word holds more than five errors, the count is set
-// to kNoRecords and the walker draws that op inline instead.
+// Noise pre-pass: one workgroup per (noise execution, group of up to
+// kGenTiles tiles).  The prefix test runs over all (16-slot group, word)
+// candidates of the group's tiles, flattened so that the lanes stay busy;
+// surviving (slot, word) pairs are queued in LDS per tile and then expanded
+// into records, again flattened over the tiles.  If a tile's queue would
+// exceed its reserved records (or its LDS queue), or one of its words holds
+// more than five errors, its count is set to kNoRecords and the walker draws
+// that op inline for that tile instead.
 template <int T>
-__global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
-  __shared__ uint64_t queue[kGenQueue];
+__global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
+  extern __shared__ uint64_t queue[];            // [tiles of the group][g.queue_per_tile]
   __shared__ uint64_t thr[64];
-  __shared__ uint32_t s_count, s_bad;
-  const uint32_t tile = blockIdx.x, inst = blockIdx.y;
-  uint2 *meta = g.meta + (size_t)inst * g.tiles + tile;
+  __shared__ uint32_t s_cnt[kGenTiles], s_bad[kGenTiles], s_off[kGenTiles + 1];
+  const uint32_t inst = blockIdx.y;
+  const uint32_t t0 = blockIdx.x * g.tiles_per_group;
+  const uint32_t S = g.tiles - t0 < g.tiles_per_group ? g.tiles - t0 : g.tiles_per_group;
+  uint2 *meta = g.meta + (size_t)inst * g.tiles + t0;
   const uint32_t cap = g.cap[inst];
-  const uint32_t first = (uint32_t)(g.base[inst] + (uint64_t)tile * cap);
+  const uint64_t base = g.base[inst];
   if (cap == 0) {
-    if (threadIdx.x == 0) *meta = make_uint2(kNoRecords, 0u);
+    if (threadIdx.x < S) meta[threadIdx.x] = make_uint2(kNoRecords, 0u);
     return;
   }
   const DevOp op = g.ops[g.inst_pc[inst]];
@@ -405,26 +410,26 @@ __global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
   const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
   const uint64_t instr = g.inst_instr[inst];
   if (threadIdx.x < 64) thr[threadIdx.x] = g.thresholds[(size_t)op.aux * 64 + threadIdx.x];
-  if (threadIdx.x == 0) { s_count = 0; s_bad = 0; }
+  if (threadIdx.x < S) { s_cnt[threadIdx.x] = 0; s_bad[threadIdx.x] = 0; }
   __syncthreads();
   const uint64_t cut = thr[63] >> 48;
   const float p_est = (float)(0ull - thr[0]) * 0x1p-64f + (thr[0] == 0 ? 1.0f : 0.0f);
   const float inv_log2_keep = 1.0f / (log1pf(-p_est) * 1.44269504088896340736f);
-  const uint64_t tw0 = (uint64_t)tile * T;
-  const int valid = (int)((g.num_words - tw0) < (uint64_t)T ? (g.num_words - tw0) : (uint64_t)T);
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
   const uint32_t g_lo = s_lo >> 4, ngroups = ((s_hi - 1) >> 4) - g_lo + 1;
-  const uint32_t cand = ngroups * T;
-  const uint32_t limit = cap < kGenQueue ? cap : kGenQueue;
+  const uint32_t cand = ngroups * T;                 // candidates per tile
+  const uint32_t qcap = cap < g.queue_per_tile ? cap : g.queue_per_tile;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t rounds = (cand + blockDim.x - 1) / blockDim.x;      // uniform
-  for (uint32_t rd = 0; rd < rounds; rd++) {
-    const uint32_t c = rd * blockDim.x + threadIdx.x;
-    const uint32_t grp = g_lo + c / T;
-    const int j = (int)(c % T);
+  const uint32_t all_cand = S * cand;
+  for (uint32_t c0 = 0; c0 < all_cand; c0 += blockDim.x) {       // uniform trip count
+    const uint32_t c = c0 + threadIdx.x;
+    const uint32_t ts = c / cand, cc = c % cand;
+    const uint32_t grp = g_lo + cc / T;
+    const int j = (int)(cc % T);
+    const uint64_t tw0 = (uint64_t)(t0 + ts) * T;
     uint32_t mask = 0;
     U64x4 r{{0, 0, 0, 0}};
-    if (c < cand && j < valid) {
+    if (c < all_cand && tw0 + j < g.num_words) {
       r = philox_call(instr, grp, g.word0 + tw0 + j, PURPOSE_NOISE_PREFIX << 32, g.seed);
 #pragma unroll
       for (uint32_t b = 0; b < 16; b++) {
@@ -433,53 +438,78 @@ __global__ void __launch_bounds__(1024) k_noise_gen(NoiseGenParams g) {
         if (s >= s_lo && s < s_hi && v16 >= cut) mask |= 1u << b;
       }
     }
-    // One LDS atomic per wave: lanes take consecutive slots of the wave's range.
-    uint32_t wtotal;
-    const uint32_t wfirst = wave_exclusive_scan((uint32_t)__builtin_popcount(mask), lane, &wtotal);
-    uint32_t wbase = 0;
-    if (lane == 0 && wtotal) wbase = atomicAdd(&s_count, wtotal);
-    wbase = __shfl(wbase, 0, 64);
-    uint32_t idx = wbase + wfirst;
+    // Queue positions: one LDS atomic per (wave, tile) present in the wave.
+    bool pending = mask != 0;
+    uint32_t idx = 0;
+    while (true) {
+      const uint64_t act = __ballot(pending);
+      if (!act) break;
+      const uint32_t s0 = __shfl(ts, __ffsll((unsigned long long)act) - 1, 64);
+      const bool mine = pending && ts == s0;
+      uint32_t wtotal;
+      const uint32_t first = wave_exclusive_scan(mine ? (uint32_t)__builtin_popcount(mask) : 0u, lane, &wtotal);
+      uint32_t wbase = 0;
+      if (lane == 0) wbase = atomicAdd(&s_cnt[s0], wtotal);
+      wbase = __shfl(wbase, 0, 64);
+      if (mine) {
+        idx = wbase + first;
+        pending = false;
+      }
+    }
+    uint64_t *q = queue + (size_t)ts * g.queue_per_tile;
     while (mask) {
       const uint32_t b = (uint32_t)__builtin_ctz(mask);
       mask &= mask - 1;
-      if (idx < limit) {
+      if (idx < qcap) {
         const uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
-        queue[idx] = ((uint64_t)(grp * 16 + b - s_lo) << 24) | ((uint64_t)j << 16) | v16;
+        q[idx] = ((uint64_t)(grp * 16 + b - s_lo) << 24) | ((uint64_t)j << 16) | v16;
       }
       idx++;
     }
   }
   __syncthreads();
-  const uint32_t total = s_count;
-  if (total > limit) {
-    if (threadIdx.x == 0) *meta = make_uint2(kNoRecords, 0u);
-    return;
+  // Flatten the queues of the tiles that fit (a tile that overflows draws inline).
+  if (threadIdx.x == 0) {
+    uint32_t off = 0;
+    for (uint32_t t = 0; t < S; t++) {
+      s_off[t] = off;
+      off += s_cnt[t] <= qcap ? s_cnt[t] : 0u;
+    }
+    s_off[S] = off;
   }
+  __syncthreads();
+  const uint32_t total = s_off[S];
   const uint32_t *tg = g.targets + op.toff;
-  uint4 *out = g.rec + first;
   for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const uint64_t q = queue[e];
-    const uint32_t k = (uint32_t)(q >> 24);
-    const int j = (int)((q >> 16) & 0xFF);
+    uint32_t ts = 0;
+    while (ts + 1 < S && s_off[ts + 1] <= e) ts++;
+    const uint32_t le = e - s_off[ts];
+    const uint64_t qe = queue[(size_t)ts * g.queue_per_tile + le];
+    const uint32_t k = (uint32_t)(qe >> 24);
+    const int j = (int)((qe >> 16) & 0xFF);
+    const uint64_t tw0 = (uint64_t)(t0 + ts) * T;
     uint64_t packed = 0;
     int nh = 0;
-    noise_walk(K, g.seed, instr, (uint64_t)s_lo + k, g.word0 + tw0 + j, thr, inv_log2_keep, q & 0xFFFF,
+    noise_walk(K, g.seed, instr, (uint64_t)s_lo + k, g.word0 + tw0 + j, thr, inv_log2_keep, qe & 0xFFFF,
                PhiloxCall(), [&](int pos, uint32_t ch) {
                  if (nh < 5) packed |= ((uint64_t)pos | ((uint64_t)ch << 6)) << (3 + 11 * nh);
                  nh++;
                });
-    if (nh > 5) s_bad = 1;
+    if (nh > 5) s_bad[ts] = 1;
     packed |= (uint64_t)(nh < 5 ? nh : 5);
     uint4 rec;
     rec.x = (code == OP_NOISE_DEP2 ? tg[2 * k] : tg[k]) | ((uint32_t)j << 27);
     rec.y = code == OP_NOISE_DEP2 ? tg[2 * k + 1] : 0u;
     rec.z = (uint32_t)packed;
     rec.w = (uint32_t)(packed >> 32);
-    out[e] = rec;
+    g.rec[base + (uint64_t)(t0 + ts) * cap + le] = rec;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *meta = make_uint2(s_bad ? kNoRecords : total, first);
+  if (threadIdx.x < S) {
+    const uint32_t t = threadIdx.x;
+    const bool ok = s_cnt[t] <= qcap && !s_bad[t];
+    meta[t] = make_uint2(ok ? s_cnt[t] : kNoRecords, (uint32_t)(base + (uint64_t)(t0 + t) * cap));
+  }
 }
 
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
@@ -720,15 +750,19 @@ int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits) {
 hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t instances, uint32_t threads,
                             hipStream_t stream) {
   if (instances == 0 || g.tiles == 0) return hipSuccess;
-  if (instances > 65535 || threads == 0 || threads % 64 || threads > 1024) return hipErrorInvalidValue;
-  dim3 grid(g.tiles, instances), block(threads);
+  if (instances > 65535 || threads == 0 || threads % 64 || threads > 512 || g.tiles_per_group == 0 ||
+      g.tiles_per_group > kGenTiles || g.queue_per_tile == 0 ||
+      (size_t)g.tiles_per_group * g.queue_per_tile > kGenQueue)
+    return hipErrorInvalidValue;
+  dim3 grid((g.tiles + g.tiles_per_group - 1) / g.tiles_per_group, instances), block(threads);
+  const size_t lds = (size_t)g.tiles_per_group * g.queue_per_tile * sizeof(uint64_t);
   switch (tile_words) {
-    case 1: hipLaunchKernelGGL(k_noise_gen<1>, grid, block, 0, stream, g); break;
-    case 2: hipLaunchKernelGGL(k_noise_gen<2>, grid, block, 0, stream, g); break;
-    case 4: hipLaunchKernelGGL(k_noise_gen<4>, grid, block, 0, stream, g); break;
-    case 8: hipLaunchKernelGGL(k_noise_gen<8>, grid, block, 0, stream, g); break;
-    case 16: hipLaunchKernelGGL(k_noise_gen<16>, grid, block, 0, stream, g); break;
-    case 32: hipLaunchKernelGGL(k_noise_gen<32>, grid, block, 0, stream, g); break;
+    case 1: hipLaunchKernelGGL(k_noise_gen<1>, grid, block, lds, stream, g); break;
+    case 2: hipLaunchKernelGGL(k_noise_gen<2>, grid, block, lds, stream, g); break;
+    case 4: hipLaunchKernelGGL(k_noise_gen<4>, grid, block, lds, stream, g); break;
+    case 8: hipLaunchKernelGGL(k_noise_gen<8>, grid, block, lds, stream, g); break;
+    case 16: hipLaunchKernelGGL(k_noise_gen<16>, grid, block, lds, stream, g); break;
+    case 32: hipLaunchKernelGGL(k_noise_gen<32>, grid, block, lds, stream, g); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
