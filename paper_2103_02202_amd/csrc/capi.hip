@@ -37,7 +37,7 @@ struct DeviceCopy {
   uint32_t *targets = nullptr;
   uint64_t *thresholds = nullptr;
   uint64_t *ref = nullptr;
-  uint32_t *det_off = nullptr, *det_idx = nullptr, *obs_off = nullptr, *obs_idx = nullptr;
+  uint32_t *det_off = nullptr, *det_idx = nullptr, *obs_off = nullptr, *obs_idx = nullptr, *det_order = nullptr;
   uint32_t *noise_pc = nullptr;
   uint64_t *noise_instr = nullptr;
 };
@@ -92,6 +92,7 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
       (e = upload(P.thresholds, &d.thresholds, s)) != hipSuccess || (e = upload(c->ref, &d.ref, s)) != hipSuccess ||
       (e = upload(P.det_offsets, &d.det_off, s)) != hipSuccess ||
       (e = upload(P.det_indices, &d.det_idx, s)) != hipSuccess ||
+      (e = upload(P.det_order, &d.det_order, s)) != hipSuccess ||
       (e = upload(P.obs_offsets, &d.obs_off, s)) != hipSuccess ||
       (e = upload(P.obs_indices, &d.obs_idx, s)) != hipSuccess ||
       (e = upload(P.noise_pc, &d.noise_pc, s)) != hipSuccess ||
@@ -347,9 +348,15 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.rec = d_rec;
     // Each workgroup takes as many tiles of one execution as its LDS queue
     // holds at the largest reservation, so that its lanes stay busy.
-    g.tiles_per_group = std::max<uint32_t>(1, std::min<uint32_t>(kGenTiles, kGenQueue / max_cap));
+    // (STIM_GEN_TILES and STIM_GEN_THREADS override the choice, for tuning.)
+    uint32_t want_tiles = kGenTiles, gen_threads = 512;
+    if (const char *v = std::getenv("STIM_GEN_TILES")) want_tiles = std::max(1, std::min(atoi(v), (int)kGenTiles));
+    if (const char *v = std::getenv("STIM_GEN_THREADS")) {
+      const int t = atoi(v);
+      if (t >= 64 && t <= 512 && t % 64 == 0) gen_threads = (uint32_t)t;
+    }
+    g.tiles_per_group = std::max<uint32_t>(1, std::min<uint32_t>(want_tiles, kGenQueue / max_cap));
     g.queue_per_tile = kGenQueue / g.tiles_per_group;
-    const uint32_t gen_threads = 256;
     if (timed) (void)hipEventRecord(tev.start, s);
     if ((e = launch_noise_gen(g, cfg.tile_words, (uint32_t)ninst, gen_threads, s)) != hipSuccess) {
       free_prepass();
@@ -485,9 +492,11 @@ hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
     if (r.mode != 1) continue;
     DeviceCopy &d = r.c->dev[pl.device];
     const uint64_t W = (r.num_shots + 63) / 64;
-    e = launch_parity(pl.flips[i], W, d.det_off, d.det_idx, (uint32_t)r.c->prog.num_detectors, r.out0, s);
+    e = launch_parity(pl.flips[i], W, d.det_off, d.det_idx, d.det_order, (uint32_t)r.c->prog.num_detectors,
+                      r.out0, s);
     if (e == hipSuccess && r.out1)
-      e = launch_parity(pl.flips[i], W, d.obs_off, d.obs_idx, (uint32_t)r.c->prog.num_observables, r.out1, s);
+      e = launch_parity(pl.flips[i], W, d.obs_off, d.obs_idx, nullptr, (uint32_t)r.c->prog.num_observables, r.out1,
+                        s);
     if (e != hipSuccess) return e;
   }
   return e;
@@ -729,8 +738,8 @@ void stim_circuit_free(stim_circuit *c) {
   for (auto &kv : c->dev) {
     (void)hipSetDevice(kv.first);
     DeviceCopy &d = kv.second;
-    void *ptrs[] = {d.ops,     d.targets, d.thresholds, d.ref,      d.det_off,
-                    d.det_idx, d.obs_off, d.obs_idx,    d.noise_pc, d.noise_instr};
+    void *ptrs[] = {d.ops,     d.targets, d.thresholds, d.ref,      d.det_off,   d.det_idx,
+                    d.obs_off, d.obs_idx, d.det_order,  d.noise_pc, d.noise_instr};
     for (void *p : ptrs) if (p) (void)hipFree(p);
   }
   if (!c->dev.empty()) (void)hipSetDevice(cur);
@@ -794,11 +803,11 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   hipError_t e = hipMallocAsync((void **)&flips, bytes, s);
   if (e != hipSuccess) return set_error(STIM_E_OOM, "flip scratch allocation failed");
   rc = run_frame(c, d, seed, shot_offset, num_shots, nullptr, flips, s);
-  if (!rc && (e = launch_parity(flips, W, d->det_off, d->det_idx, (uint32_t)c->prog.num_detectors, out_det, s)) !=
-                 hipSuccess)
+  if (!rc && (e = launch_parity(flips, W, d->det_off, d->det_idx, d->det_order, (uint32_t)c->prog.num_detectors,
+                                out_det, s)) != hipSuccess)
     rc = hip_error(e, "detector kernel launch");
   if (!rc && out_obs &&
-      (e = launch_parity(flips, W, d->obs_off, d->obs_idx, (uint32_t)c->prog.num_observables, out_obs, s)) !=
+      (e = launch_parity(flips, W, d->obs_off, d->obs_idx, nullptr, (uint32_t)c->prog.num_observables, out_obs, s)) !=
           hipSuccess)
     rc = hip_error(e, "observable kernel launch");
   hipError_t fe = hipFreeAsync(flips, s);

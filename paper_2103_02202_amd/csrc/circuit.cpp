@@ -439,6 +439,33 @@ Program compile_program(const std::vector<Node> &tree) {
     L.prog.obs_offsets.push_back((uint32_t)L.prog.obs_indices.size());
   }
   L.prog.num_observables = w.observables.size();
+  // Detector visiting order for the event kernel.
+  {
+    Program &P = L.prog;
+    const size_t D = P.det_offsets.size() - 1;
+    std::unordered_map<uint32_t, std::vector<uint32_t>> users;   // measurement -> detectors using it
+    for (size_t d = 0; d < D; d++)
+      for (uint32_t k = P.det_offsets[d]; k < P.det_offsets[d + 1]; k++) users[P.det_indices[k]].push_back((uint32_t)d);
+    std::vector<char> seen(D, 0);
+    P.det_order.reserve(D);
+    for (size_t d0 = 0; d0 < D; d0++) {
+      uint32_t cur = (uint32_t)d0;
+      while (!seen[cur]) {
+        seen[cur] = 1;
+        P.det_order.push_back(cur);
+        uint32_t last = 0;
+        bool any = false;
+        for (uint32_t k = P.det_offsets[cur]; k < P.det_offsets[cur + 1]; k++)
+          if (!any || P.det_indices[k] > last) { last = P.det_indices[k]; any = true; }
+        if (!any) break;
+        uint32_t nxt = cur;
+        for (uint32_t e : users[last])
+          if (!seen[e]) { nxt = e; break; }
+        if (nxt == cur) break;
+        cur = nxt;
+      }
+    }
+  }
   // Noise-op executions in walk order (same control flow as the kernels).
   {
     const size_t kMaxInstances = 65535;

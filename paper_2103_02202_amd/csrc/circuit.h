@@ -77,6 +77,10 @@ struct Program {
   std::vector<uint32_t> det_indices;       // absolute measurement indices
   std::vector<uint32_t> obs_offsets;       // CSR over observables, size L + 1
   std::vector<uint32_t> obs_indices;
+  // Order in which the event kernel visits detectors: chains of detectors
+  // that share a measurement (each continues from the latest measurement of
+  // the previous one), so that a shared flip row is loaded once.
+  std::vector<uint32_t> det_order;
   uint64_t num_qubits = 0, num_measurements = 0, num_detectors = 0, num_observables = 0;
   uint64_t num_gate_targets = 0, num_noise_targets = 0, num_instructions = 0;
   uint32_t max_loop_depth = 0;

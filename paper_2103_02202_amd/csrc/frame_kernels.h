@@ -37,7 +37,7 @@ constexpr uint32_t kNoRecords = 0xFFFFFFFFu;
 // LDS queue entries of one k_noise_gen workgroup (shared by its tiles), and
 // the most tiles one workgroup takes.
 constexpr uint32_t kGenQueue = 4096;
-constexpr uint32_t kGenTiles = 8;
+constexpr uint32_t kGenTiles = 16;
 
 struct NoiseGenParams {
   const DevOp *ops;
@@ -92,7 +92,9 @@ hipError_t launch_batch(const FrameParams *reqs, const BatchItem *items, uint32_
                         const FrameConfig &cfg, uint64_t max_qubits, uint32_t blocks, hipStream_t stream);
 // Workgroups of the batch kernel that fit on one CU at once.
 int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits);
+// Detection events / observable flips: row r of `out` = XOR of the flip rows
+// idx[off[r] .. off[r+1]).  Rows are visited in `order` (NULL: 0, 1, ...).
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,
-                         uint32_t rows, uint64_t *out, hipStream_t stream);
+                         const uint32_t *order, uint32_t rows, uint64_t *out, hipStream_t stream);
 
 }  // namespace stimgpu

@@ -656,16 +656,44 @@ __global__ void __launch_bounds__(1024) k_batch(const FrameParams *__restrict__ 
 __global__ void k_fill_u32(uint32_t *ptr, uint32_t value) { *ptr = value; }
 
 // Detection events / observable flips: row r of `out` is the XOR of the flip
-// rows listed in idx[off[r] .. off[r+1]) (Sec. 5.6).
+// rows listed in idx[off[r] .. off[r+1]) (Sec. 5.6).  A thread owns VEC
+// adjacent words and walks `rows_per_block` rows in visiting order; the last
+// two flip rows it loaded stay in registers, so a row shared by consecutive
+// detectors of a chain is read from memory once.
+template <int VEC>
 __global__ void __launch_bounds__(256) k_parity(const uint64_t *__restrict__ flips, uint64_t W,
                                                  const uint32_t *__restrict__ off, const uint32_t *__restrict__ idx,
-                                                 uint32_t rows, uint32_t blocks_per_row, uint64_t *__restrict__ out) {
-  const uint32_t r = blockIdx.x / blocks_per_row;
-  const uint64_t w = (uint64_t)(blockIdx.x % blocks_per_row) * blockDim.x + threadIdx.x;
-  if (r >= rows || w >= W) return;
-  uint64_t acc = 0;
-  for (uint32_t k = off[r]; k < off[r + 1]; k++) acc ^= flips[(uint64_t)idx[k] * W + w];
-  out[(uint64_t)r * W + w] = acc;
+                                                 const uint32_t *__restrict__ order, uint32_t rows,
+                                                 uint32_t rows_per_block, uint64_t *__restrict__ out) {
+  typedef uint64_t V2 __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<VEC == 2, V2, uint64_t>::type V;
+  const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  if (w >= W) return;
+  const uint32_t r0 = blockIdx.y * rows_per_block;
+  const uint32_t r1 = rows - r0 < rows_per_block ? rows : r0 + rows_per_block;
+  uint32_t ci0 = 0xFFFFFFFFu, ci1 = 0xFFFFFFFFu;
+  V cv0 = V(0), cv1 = V(0);
+  for (uint32_t i = r0; i < r1; i++) {
+    const uint32_t r = order ? order[i] : i;
+    V acc = V(0);
+    for (uint32_t k = off[r]; k < off[r + 1]; k++) {
+      const uint32_t m = idx[k];
+      V v;
+      if (m == ci0) {
+        v = cv0;
+      } else if (m == ci1) {
+        v = cv1;
+      } else {
+        v = *reinterpret_cast<const V *>(flips + (uint64_t)m * W + w);
+        ci1 = ci0;
+        cv1 = cv0;
+        ci0 = m;
+        cv0 = v;
+      }
+      acc ^= v;
+    }
+    *reinterpret_cast<V *>(out + (uint64_t)r * W + w) = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -769,13 +797,30 @@ hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t in
 }
 
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,
-                         uint32_t rows, uint64_t *out, hipStream_t stream) {
-  if (rows == 0) return hipSuccess;
+                         const uint32_t *order, uint32_t rows, uint64_t *out, hipStream_t stream) {
+  if (rows == 0 || W == 0) return hipSuccess;
   const uint32_t threads = 256;
-  uint32_t bpr = (uint32_t)((W + threads - 1) / threads);
-  uint64_t blocks = (uint64_t)bpr * rows;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_parity, dim3((uint32_t)blocks), dim3(threads), 0, stream, flips, W, off, idx, rows, bpr, out);
+  const uint32_t rows_per_block = 8;
+  // 16-byte accesses when every row of both arrays starts 16-byte aligned.
+  const int vec = W % 2 == 0 && (uintptr_t)out % 16 == 0 && (uintptr_t)flips % 16 == 0 ? 2 : 1;
+  const uint64_t xb = (W / vec + threads - 1) / threads;
+  const uint64_t yb = (rows + rows_per_block - 1) / rows_per_block;
+  if (xb > 0x7FFFFFFFull || yb > 65535) {
+    // Very many rows: widen the row groups so that the grid's y extent fits.
+    const uint64_t rpb = (rows + 65534) / 65535;
+    if (xb > 0x7FFFFFFFull || rpb > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    const dim3 grid((uint32_t)xb, (uint32_t)((rows + rpb - 1) / rpb));
+    if (vec == 2)
+      hipLaunchKernelGGL(k_parity<2>, grid, dim3(threads), 0, stream, flips, W, off, idx, order, rows, (uint32_t)rpb, out);
+    else
+      hipLaunchKernelGGL(k_parity<1>, grid, dim3(threads), 0, stream, flips, W, off, idx, order, rows, (uint32_t)rpb, out);
+    return hipGetLastError();
+  }
+  const dim3 grid((uint32_t)xb, (uint32_t)yb);
+  if (vec == 2)
+    hipLaunchKernelGGL(k_parity<2>, grid, dim3(threads), 0, stream, flips, W, off, idx, order, rows, rows_per_block, out);
+  else
+    hipLaunchKernelGGL(k_parity<1>, grid, dim3(threads), 0, stream, flips, W, off, idx, order, rows, rows_per_block, out);
   return hipGetLastError();
 }
 
