@@ -13,6 +13,8 @@ Prints one JSON line.  Fields beyond the driver's contract:
   cpu_baseline  -- the oracle timed on this host on a bounded shot sample
   analysis_s    -- host compile + reference-sample time
   meas_mode     -- measurement-record sampling (stim_frame_sample) rate
+  formats       -- shot-major output formats (01, b8, hits, r8) of the run's
+                   detection events and record: time and bytes per second
   batch         -- the 64-circuit mix in one persistent graph-captured launch
                    vs the same requests one at a time
   serving       -- Poisson request streams over the resident d = 3..101 pool:
@@ -130,6 +132,34 @@ def bench_batch(steps: int):
             "speedup_vs_one_at_a_time": single_ms / batched_ms, "analysis_s": analysis}
 
 
+def bench_formats(det, meas, rows_det, rows_meas, shots, reps: int = 3):
+    """Shot-major output formats of the d=49 run's detection events and
+    measurement record: time per call (HIP events on the stream) and
+    algorithmic bytes (table in + formatted bytes out) per second."""
+    import torch
+    from paper_2103_02202_amd import stim_gpu
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, table, rows, fmts in (("detection_events", det, rows_det, ("b8", "r8", "hits", "01")),
+                                    ("measurement_record", meas, rows_meas, ("b8",))):
+        for fmt in fmts:
+            n = stim_gpu.stim_format_shots(table, rows, shots, fmt, None, stream)
+            buf = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+            stim_gpu.stim_format_shots(table, rows, shots, fmt, buf, stream)        # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                stim_gpu.stim_format_shots(table, rows, shots, fmt, buf, stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            moved = rows * ((shots + 63) // 64) * 8 + n
+            out[f"{name}/{fmt}"] = {"ms": ms, "out_bytes": n, "GB_per_s": moved / (ms * 1e-3) / 1e9,
+                                    "hbm_frac": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del buf
+    return out
+
+
 def bench_serving(rates=(10, 30, 100, 300, 1000)):
     import torch
     from paper_2103_02202_amd import serve, workloads
@@ -171,6 +201,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-formats", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -278,6 +309,8 @@ def main():
         "meas_mode": {"ms": pass_ms, "shot_gates_per_s": G * SHOTS / (pass_ms * 1e-3)},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
+    if not args.no_formats:
+        out["formats"] = bench_formats(det, meas, Dn, M, SHOTS)
     if not args.no_batch:
         out["batch"] = bench_batch(max(3, args.steps // 2))
     if not args.no_serving:

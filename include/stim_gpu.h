@@ -116,6 +116,29 @@ typedef struct {
  * request functions one by one. */
 int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream);
 
+/* Shot-major output formats (Sec. 5.11, "Output Format"). */
+enum {
+  STIM_FORMAT_01 = 0,    /* '0'/'1' per result, '\n' after each shot: rows + 1 bytes per shot */
+  STIM_FORMAT_B8 = 1,    /* 8 results per byte, LSB first, zero-padded: ceil(rows / 8) bytes per shot */
+  STIM_FORMAT_HITS = 2,  /* indices of the set results in decimal, ',' between, '\n' after each shot */
+  STIM_FORMAT_R8 = 3     /* per set result the zero run before it as bytes (255 = 255 zeros, continue),
+                            then the zero run to the end of the shot the same way */
+};
+
+/* Writes shots [0, num_shots) of a measurement-major table in a shot-major
+ * format (the two sparse formats, hits and r8, are this library's reading of
+ * the formats the paper names without defining).  table: device
+ * [rows][ceil(num_shots / 64)] uint64 as the samplers write it (a record,
+ * events or observables); out: device buffer of out_cap bytes, or NULL with
+ * out_cap 0 to only ask for the size.  *out_len (host) receives the number of
+ * bytes of the whole output.  Dense formats (01, b8) have a fixed size and the
+ * call is asynchronous on `hip_stream`; sparse formats (hits, r8) are sized by
+ * a counting pass, so the call waits for the stream.  Returns
+ * STIM_E_INVALID_ARG (writing nothing) if out_cap < *out_len, and for an 01
+ * or b8 output that is not 4-byte aligned. */
+int stim_format_shots(const uint64_t *table, uint64_t rows, uint64_t num_shots, int format, uint8_t *out,
+                      uint64_t out_cap, uint64_t *out_len, void *hip_stream);
+
 /* Per-kernel timing of sampling passes (stim_frame_sample and
  * stim_detector_sample; not batched launches).  stim_kernel_timing(1) discards
  * what was collected and starts recording HIP events on each pass's stream

@@ -14,6 +14,7 @@
 
 #include "stim_gpu.h"
 #include "circuit.h"
+#include "format_kernels.h"
 #include "frame_kernels.h"
 
 using namespace stimgpu;
@@ -538,11 +539,17 @@ void batch_params(BatchPlan &pl, std::vector<FrameParams> &params, uint64_t *fli
 
 // Splits requests into those that run inside the persistent launch (frames
 // fit in LDS) and the rest; returns the flip scratch size in words.
+// A noisy request with at least this many shot-gates runs through the
+// single-request path: its noise pre-pass outweighs sharing a launch.
+constexpr double kSingleWork = 4e9;
+
 uint64_t partition_requests(BatchPlan &pl) {
   uint64_t total_flips = 0;
   for (size_t i = 0; i < pl.reqs.size(); i++) {
     const stim_request &r = pl.reqs[i];
-    if (batch_fits(r.c->prog.num_qubits, 1, 256)) {
+    const double work = (double)r.c->prog.num_gate_targets * (double)r.num_shots;
+    const bool big_noisy = r.c->prog.num_noise_targets > 0 && work >= kSingleWork && !r.c->prog.noise_pc.empty();
+    if (!big_noisy && batch_fits(r.c->prog.num_qubits, 1, 256)) {
       pl.batched.push_back(i);
       pl.max_n = std::max(pl.max_n, r.c->prog.num_qubits);
       if (r.mode == 1) total_flips += std::max<uint64_t>(r.c->prog.num_measurements, 1) * ((r.num_shots + 63) / 64);
@@ -813,6 +820,74 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   hipError_t fe = hipFreeAsync(flips, s);
   if (!rc && fe != hipSuccess) rc = hip_error(fe, "hipFreeAsync");
   return rc;
+}
+
+int stim_format_shots(const uint64_t *table, uint64_t rows, uint64_t num_shots, int format, uint8_t *out,
+                      uint64_t out_cap, uint64_t *out_len, void *hip_stream) {
+  if (!out_len) return set_error(STIM_E_INVALID_ARG, "out_len is NULL");
+  *out_len = 0;
+  if (format < STIM_FORMAT_01 || format > STIM_FORMAT_R8) return set_error(STIM_E_INVALID_ARG, "unknown format");
+  if (num_shots == 0) return set_error(STIM_E_INVALID_ARG, "num_shots must be positive");
+  if (rows >= (1ull << 31) || num_shots >= (1ull << 40)) return set_error(STIM_E_UNSUPPORTED, "table too large");
+  if (rows > 0 && !is_device_pointer(table)) return set_error(STIM_E_INVALID_ARG, "table is not a device pointer");
+  if (out_cap > 0 && !is_device_pointer(out)) return set_error(STIM_E_INVALID_ARG, "out is not a device pointer");
+  if (out_cap > 0 && (format == STIM_FORMAT_B8 || format == STIM_FORMAT_01) && (uintptr_t)out % 4)
+    return set_error(STIM_E_INVALID_ARG, "01 and b8 outputs must be 4-byte aligned");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const uint64_t W = (num_shots + 63) / 64;
+  const bool dense = format == STIM_FORMAT_01 || format == STIM_FORMAT_B8;
+  if (dense) {
+    const uint64_t per = format == STIM_FORMAT_B8 ? (rows + 7) / 8 : rows + 1;
+    *out_len = per * num_shots;
+    if (out_cap < *out_len) {
+      if (out_cap == 0 && !out) return STIM_OK;          // size query
+      return set_error(STIM_E_INVALID_ARG, "output buffer too small");
+    }
+    if (*out_len == 0) return STIM_OK;
+  }
+  hipError_t e;
+  uint64_t *T = nullptr, *lens = nullptr, *offs = nullptr, *total = nullptr, *sums = nullptr;
+  auto release = [&]() {
+    void *ptrs[] = {T, lens, offs, total, sums};
+    for (void *q : ptrs) if (q) (void)hipFreeAsync(q, s);
+  };
+  if ((e = hipMallocAsync((void **)&T, std::max<uint64_t>(num_shots * transpose_stride(rows), 1) * 8, s)) !=
+      hipSuccess)
+    return set_error(STIM_E_OOM, "transpose scratch allocation failed");
+  if ((e = launch_transpose(table, rows, W, num_shots, T, s)) != hipSuccess) {
+    release();
+    return hip_error(e, "transpose launch");
+  }
+  if (dense) {
+    e = launch_dense_format(T, rows, num_shots, format == STIM_FORMAT_B8, out, s);
+    release();
+    return e == hipSuccess ? STIM_OK : hip_error(e, "format launch");
+  }
+  const int r8 = format == STIM_FORMAT_R8;
+  if ((e = hipMallocAsync((void **)&lens, num_shots * 8, s)) != hipSuccess ||
+      (e = hipMallocAsync((void **)&offs, num_shots * 8, s)) != hipSuccess ||
+      (e = hipMallocAsync((void **)&total, 8, s)) != hipSuccess ||
+      (e = hipMallocAsync((void **)&sums, kScanBlocks * 8, s)) != hipSuccess) {
+    release();
+    return set_error(STIM_E_OOM, "format scratch allocation failed");
+  }
+  uint64_t host_total = 0;
+  if ((e = launch_sparse_format(T, rows, num_shots, r8, lens, nullptr, nullptr, s)) != hipSuccess ||
+      (e = launch_scan(lens, num_shots, offs, sums, total, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(&host_total, total, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    release();
+    return hip_error(e, "format size pass");
+  }
+  *out_len = host_total;
+  if (out_cap < host_total) {
+    release();
+    if (out_cap == 0 && !out) return STIM_OK;            // size query
+    return set_error(STIM_E_INVALID_ARG, "output buffer too small");
+  }
+  e = launch_sparse_format(T, rows, num_shots, r8, lens, offs, out, s);
+  release();
+  return e == hipSuccess ? STIM_OK : hip_error(e, "format launch");
 }
 
 int stim_kernel_timing(int enable) {

@@ -1,0 +1,405 @@
+// Shot-major output formats (Sec. 5.11) from the sampler's measurement-major
+// tables.
+//
+// A table is [rows][W] uint64 with bit j of word w = shot 64 w + j.  The
+// formats are written per shot, so the first step transposes the table in
+// 64 x 64 bit blocks into a shot-major scratch table
+// T[shot][nchunks] (bit i of T[s][c] = row 64 c + i of shot s).  Dense formats
+// (01, b8) then map T to the output byte by byte; sparse formats (hits, r8)
+// take one wave per shot twice: once to measure each shot's output, and,
+// after a prefix sum over the shots, once to write it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "format_kernels.h"
+
+namespace stimgpu {
+
+namespace {
+
+// Maps a workgroup index so that the workgroups of one XCD take consecutive
+// blocks (the hardware deals workgroups round-robin over the 8 XCDs).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
+  const uint32_t X = 8;
+  const uint32_t xcd = bid % X, local = bid / X;
+  const uint32_t per = nblocks / X, rem = nblocks % X;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Transposes a 64 x 64 bit block held one row per lane: on entry lane l holds
+// row l (bit s = column s); on exit lane s holds column s (bit l = row l).
+// Recursive exchange of off-diagonal blocks of halving size.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane) {
+  uint64_t m = 0x00000000FFFFFFFFull;
+#pragma unroll
+  for (int j = 32; j != 0; j >>= 1) {
+    const uint64_t other = shfl_xor64(x, j);
+    if ((lane & j) == 0) {
+      const uint64_t t = ((x >> j) ^ other) & m;
+      x ^= t << j;
+    } else {
+      const uint64_t t = ((other >> j) ^ x) & m;
+      x ^= t;
+    }
+    m ^= m << (j >> 1);
+  }
+  return x;
+}
+
+// One workgroup (1024 threads) per block of 4 x 64 rows x 16 words:
+// coalesced 128-byte row segments into LDS, then each wave transposes the four
+// 64 x 64 blocks of one word column and writes each shot's four chunks as
+// 32 contiguous bytes (T rows are padded to a multiple of four chunks).
+__global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__ table, uint64_t rows, uint64_t W,
+                                                    uint64_t shots, uint32_t nchunks, uint32_t tstride,
+                                                    uint64_t *__restrict__ T) {
+  __shared__ uint64_t tile[256][17];
+  const uint32_t ngroups = (nchunks + 3) / 4;
+  // Chunk-group-fastest order: workgroups on one XCD at the same time fill
+  // neighbouring pieces of the same T rows.
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t cg = b % ngroups, wb = b / ngroups;
+  const uint64_t w0 = (uint64_t)wb * 16;
+  {
+    const uint32_t rr = threadIdx.x >> 4, ww = threadIdx.x & 15;
+    const uint64_t w = w0 + ww;
+#pragma unroll
+    for (int h = 0; h < 4; h++) {
+      const uint64_t r = (uint64_t)cg * 256 + h * 64 + rr;
+      tile[h * 64 + rr][ww] = (r < rows && w < W) ? table[r * W + w] : 0;
+    }
+  }
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, k = threadIdx.x >> 6;
+  typedef uint64_t V2 __attribute__((ext_vector_type(2)));
+  V2 y0, y1;
+  y0.x = transpose64(tile[lane][k], lane);
+  y0.y = transpose64(tile[64 + lane][k], lane);
+  y1.x = transpose64(tile[128 + lane][k], lane);
+  y1.y = transpose64(tile[192 + lane][k], lane);
+  const uint64_t s = (w0 + k) * 64 + lane;
+  if (s < shots) {
+    V2 *dst = reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * 4);
+    dst[0] = y0;
+    dst[1] = y1;
+  }
+}
+
+// b8: shot s's bytes are the first nbytes bytes of T[s] (T rows are
+// little-endian bit strings), packed back to back.  A thread writes one
+// aligned 4-byte word of the output that lies inside row s, assembled from
+// two aligned words of T; the at most three bytes at either end of a row that
+// share an output word with the neighbouring row are written singly.
+__global__ void __launch_bounds__(256) k_b8(const uint64_t *__restrict__ T, uint32_t tstride, uint64_t shots,
+                                            uint64_t nbytes, uint8_t *__restrict__ out) {
+  const uint32_t *src32 = reinterpret_cast<const uint32_t *>(T);
+  const uint8_t *src8 = reinterpret_cast<const uint8_t *>(T);
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // output word within the row's span
+  for (uint64_t s = blockIdx.y; s < shots; s += gridDim.y) {
+    const uint64_t a0 = s * nbytes, a1 = a0 + nbytes;                    // row s occupies [a0, a1)
+    const uint64_t first = (a0 + 3) / 4, last = a1 / 4;                  // whole output words [first, last)
+    const uint64_t tw = (uint64_t)s * tstride * 2;                       // row s in 32-bit words of T
+    const uint64_t ow = first + q;
+    if (ow < last) {
+      const uint64_t b = ow * 4 - a0;                                    // byte offset inside row s
+      const uint32_t sh = (uint32_t)(b & 3) * 8;
+      const uint32_t lo = src32[tw + (b >> 2)];
+      const uint32_t hi = sh ? src32[tw + (b >> 2) + 1] : 0u;
+      const uint32_t v = sh ? (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) : lo;
+      reinterpret_cast<uint32_t *>(out)[ow] = v;
+    }
+    if (q < 4) {                                                         // ragged ends of the row
+      const uint64_t head = first * 4 - a0 < nbytes ? first * 4 - a0 : nbytes;
+      if (q < head) out[a0 + q] = src8[s * tstride * 8 + q];
+      const uint64_t tail_start = last * 4 > a0 + head ? last * 4 : a0 + head;
+      if (tail_start + q < a1) out[tail_start + q] = src8[s * tstride * 8 + (tail_start + q - a0)];
+    }
+  }
+}
+
+// 01: one character per row and a newline per shot.  As for b8, a thread
+// writes one aligned 4-byte word of the output lying inside shot s's line
+// (built from four result bits), and the ragged ends are written singly.
+__device__ __forceinline__ uint8_t char01(const uint64_t *row, uint64_t r, uint64_t rows) {
+  return r < rows ? (uint8_t)('0' + ((row[r >> 6] >> (r & 63)) & 1)) : (uint8_t)'\n';
+}
+
+__global__ void __launch_bounds__(256) k_01(const uint64_t *__restrict__ T, uint32_t tstride, uint64_t shots,
+                                            uint64_t rows, uint8_t *__restrict__ out) {
+  const uint64_t width = rows + 1;
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t s = blockIdx.y; s < shots; s += gridDim.y) {
+    const uint64_t *row = T + s * tstride;
+    const uint64_t a0 = s * width, a1 = a0 + width;
+    const uint64_t first = (a0 + 3) / 4, last = a1 / 4;
+    const uint64_t ow = first + q;
+    if (ow < last) {
+      const uint64_t r = ow * 4 - a0;                  // first row of this word
+      uint32_t v;
+      if (r + 4 <= rows) {
+        const uint32_t sh = (uint32_t)(r & 63);
+        uint64_t bits = row[r >> 6] >> sh;
+        if (sh > 60) bits |= row[(r >> 6) + 1] << (64 - sh);
+        v = 0x30303030u | (uint32_t)(bits & 1) | (uint32_t)((bits >> 1) & 1) << 8 |
+            (uint32_t)((bits >> 2) & 1) << 16 | (uint32_t)((bits >> 3) & 1) << 24;
+      } else {
+        v = 0;
+        for (uint32_t k = 0; k < 4; k++) v |= (uint32_t)char01(row, r + k, rows) << (8 * k);
+      }
+      reinterpret_cast<uint32_t *>(out)[ow] = v;
+    }
+    if (q < 4) {                                       // ragged ends of the line
+      const uint64_t head = first * 4 - a0 < width ? first * 4 - a0 : width;
+      if (q < head) out[a0 + q] = char01(row, q, rows);
+      const uint64_t tail_start = last * 4 > a0 + head ? last * 4 : a0 + head;
+      if (tail_start + q < a1) out[tail_start + q] = char01(row, tail_start + q - a0, rows);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t decimal_digits(uint32_t v) {
+  return v < 10u ? 1 : v < 100u ? 2 : v < 1000u ? 3 : v < 10000u ? 4 : v < 100000u ? 5 : v < 1000000u ? 6
+       : v < 10000000u ? 7 : v < 100000000u ? 8 : v < 1000000000u ? 9 : 10;
+}
+
+// Bytes of an r8 run of n zeros (n / 255 continuation bytes and the rest).
+__device__ __forceinline__ uint64_t r8_bytes(uint64_t n) { return n / 255 + 1; }
+
+// Exclusive sum over the lanes of a wave (32-bit); *total = the wave's sum.
+__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v, uint32_t lane, uint32_t *total) {
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// Inclusive max over lanes 0..lane.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v, uint32_t lane) {
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d && y > x) x = y;
+  }
+  return x;
+}
+
+// Sparse formats, one wave per shot; chunk c of the shot goes to lane c % 64
+// in round c / 64, so that each round's output is a contiguous, in-order
+// piece.  WRITE = false: lens[s] = the shot's byte count; WRITE = true: the
+// bytes, at out + offs[s].
+template <bool R8, bool WRITE>
+__global__ void __launch_bounds__(256) k_sparse(const uint64_t *__restrict__ T, uint32_t nchunks, uint32_t tstride,
+                                                uint64_t shots, uint64_t rows, uint64_t *__restrict__ lens,
+                                                const uint64_t *__restrict__ offs, uint8_t *__restrict__ out) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t s = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (s >= shots) return;                          // whole waves leave together
+  const uint64_t *row = T + s * tstride;
+  uint64_t base = WRITE ? offs[s] : 0;             // output bytes so far
+  // Set results are handled as index + 1 (0: none), in 32 bits (rows < 2^32).
+  uint32_t prev1 = 0;                              // last set result before this round, + 1
+  uint32_t nhits_before = 0;
+  for (uint32_t c0 = 0; c0 < nchunks; c0 += 64) {
+    const uint32_t c = c0 + lane;
+    const uint64_t x = c < nchunks ? row[c] : 0;
+    const uint32_t hit0 = c * 64;
+    // The last set result before this lane's chunk (r8) or the number of set
+    // results before it (hits: all but the first get a comma).
+    uint32_t p1 = prev1, k = 0, hits_total = 0;
+    if (R8) {
+      const uint32_t last1 = x ? hit0 + 64 - (uint32_t)__builtin_clzll(x) : 0u;
+      const uint32_t incl = wave_inclusive_max(last1 > prev1 ? last1 : prev1, lane);
+      const uint32_t up = __shfl_up(incl, 1, 64);
+      p1 = lane == 0 ? prev1 : up;
+      prev1 = __shfl(incl, 63, 64);
+    } else {
+      k = wave_exclusive_sum((uint32_t)__builtin_popcountll(x), lane, &hits_total) + nhits_before;
+      nhits_before += hits_total;
+    }
+    uint32_t n = 0;
+    {
+      uint32_t q1 = p1, kk = k;
+      for (uint64_t m = x; m; m &= m - 1) {
+        const uint32_t i = hit0 + (uint32_t)__builtin_ctzll(m);
+        n += R8 ? (uint32_t)r8_bytes(i - q1) : decimal_digits(i) + (kk > 0 ? 1u : 0u);
+        q1 = i + 1;
+        kk++;
+      }
+    }
+    uint32_t total;
+    const uint32_t before = wave_exclusive_sum(n, lane, &total);
+    if (WRITE && x) {
+      uint8_t *o = out + base + before;
+      uint32_t q1 = p1, kk = k;
+      for (uint64_t m = x; m; m &= m - 1) {
+        const uint32_t i = hit0 + (uint32_t)__builtin_ctzll(m);
+        if (R8) {
+          uint32_t run = i - q1;
+          for (; run >= 255; run -= 255) *o++ = 255;
+          *o++ = (uint8_t)run;
+        } else {
+          if (kk > 0) *o++ = ',';
+          const uint32_t d = decimal_digits(i);
+          uint32_t v = i;
+          for (uint32_t q = d; q > 0; q--) {
+            o[q - 1] = (uint8_t)('0' + v % 10u);
+            v /= 10u;
+          }
+          o += d;
+        }
+        q1 = i + 1;
+        kk++;
+      }
+    }
+    base += total;
+  }
+  const int64_t prev = (int64_t)prev1 - 1;
+  // Closing bytes: r8's run to the end of the shot; hits' newline.
+  const uint64_t tail = R8 ? r8_bytes(rows - (uint64_t)(prev + 1)) : 1;
+  (void)nhits_before;
+  if (!WRITE) {
+    if (lane == 0) lens[s] = base + tail;
+  } else if (lane == 0) {
+    if (R8) {
+      uint64_t run = rows - (uint64_t)(prev + 1);
+      uint8_t *o = out + base;
+      for (; run >= 255; run -= 255) *o++ = 255;
+      *o = (uint8_t)run;
+    } else {
+      out[base] = '\n';
+    }
+  }
+}
+
+// Exclusive prefix sum of n values in three steps: each block sums its
+// contiguous segment; one block scans the block sums; each block scans its
+// segment from its offset.  *total = the sum of all.
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *tmp, uint64_t *total) {
+  tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
+    const uint64_t y = threadIdx.x >= d ? tmp[threadIdx.x - d] : 0;
+    __syncthreads();
+    tmp[threadIdx.x] += y;
+    __syncthreads();
+  }
+  const uint64_t incl = tmp[threadIdx.x];
+  *total = tmp[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(256) k_scan_partial(const uint64_t *__restrict__ in, uint64_t n, uint64_t seg,
+                                                      uint64_t *__restrict__ sums) {
+  __shared__ uint64_t tmp[256];
+  const uint64_t lo = blockIdx.x * seg, hi = lo + seg < n ? lo + seg : n;
+  uint64_t v = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v += in[i];
+  uint64_t total;
+  block_exclusive_scan(v, tmp, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint64_t *__restrict__ sums, uint32_t nblocks,
+                                                   uint64_t *__restrict__ total) {
+  __shared__ uint64_t tmp[1024];
+  const uint64_t v = threadIdx.x < nblocks ? sums[threadIdx.x] : 0;
+  uint64_t t;
+  const uint64_t ex = block_exclusive_scan(v, tmp, &t);
+  if (threadIdx.x < nblocks) sums[threadIdx.x] = ex;
+  if (threadIdx.x == 0) *total = t;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const uint64_t *__restrict__ in, uint64_t n, uint64_t seg,
+                                                    const uint64_t *__restrict__ sums, uint64_t *__restrict__ out) {
+  __shared__ uint64_t tmp[256];
+  const uint64_t lo = blockIdx.x * seg, hi = lo + seg < n ? lo + seg : n;
+  uint64_t carry = sums[blockIdx.x];
+  for (uint64_t b = lo; b < hi; b += blockDim.x) {
+    const uint64_t i = b + threadIdx.x;
+    const uint64_t v = i < hi ? in[i] : 0;
+    uint64_t t;
+    const uint64_t ex = block_exclusive_scan(v, tmp, &t);
+    if (i < hi) out[i] = carry + ex;
+    carry += t;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_transpose(const uint64_t *table, uint64_t rows, uint64_t W, uint64_t shots, uint64_t *T,
+                            hipStream_t stream) {
+  const uint64_t nchunks = (rows + 63) / 64, ngroups = (nchunks + 3) / 4, wblocks = (W + 15) / 16;
+  const uint64_t blocks = ngroups * wblocks;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFull || nchunks > 0x3FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose, dim3((uint32_t)blocks), dim3(1024), 0, stream, table, rows, W, shots,
+                     (uint32_t)nchunks, (uint32_t)transpose_stride(rows), T);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_format(const uint64_t *T, uint64_t rows, uint64_t shots, int b8, uint8_t *out,
+                               hipStream_t stream) {
+  const uint64_t width = b8 ? (rows + 7) / 8 : rows + 1;
+  const uint64_t xb = (width / 4 + 1 + 255) / 256;
+  if (shots == 0) return hipSuccess;
+  if (xb > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const uint32_t tstride = (uint32_t)transpose_stride(rows);
+  // Each block walks many shots, so that a few thousand blocks cover the output.
+  const uint64_t yb = std::max<uint64_t>(1, std::min<uint64_t>(shots, std::max<uint64_t>(1, 16384 / xb)));
+  const dim3 grid((uint32_t)xb, (uint32_t)yb);
+  if (b8)
+    hipLaunchKernelGGL(k_b8, grid, dim3(256), 0, stream, T, tstride, shots, width, out);
+  else
+    hipLaunchKernelGGL(k_01, grid, dim3(256), 0, stream, T, tstride, shots, rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sparse_format(const uint64_t *T, uint64_t rows, uint64_t shots, int r8, uint64_t *lens,
+                                const uint64_t *offs, uint8_t *out, hipStream_t stream) {
+  const uint64_t nchunks = (rows + 63) / 64;
+  const uint64_t blocks = (shots + 3) / 4;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFull || nchunks > 0x3FFFFFFFull) return hipErrorInvalidValue;
+  const uint32_t tstride = (uint32_t)transpose_stride(rows);
+  const bool write = offs != nullptr;
+  const dim3 grid((uint32_t)blocks), block(256);
+  if (r8 && write)
+    hipLaunchKernelGGL((k_sparse<true, true>), grid, block, 0, stream, T, (uint32_t)nchunks, tstride, shots, rows,
+                       lens, offs, out);
+  else if (r8)
+    hipLaunchKernelGGL((k_sparse<true, false>), grid, block, 0, stream, T, (uint32_t)nchunks, tstride, shots, rows,
+                       lens, offs, out);
+  else if (write)
+    hipLaunchKernelGGL((k_sparse<false, true>), grid, block, 0, stream, T, (uint32_t)nchunks, tstride, shots, rows,
+                       lens, offs, out);
+  else
+    hipLaunchKernelGGL((k_sparse<false, false>), grid, block, 0, stream, T, (uint32_t)nchunks, tstride, shots, rows,
+                       lens, offs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint64_t *in, uint64_t n, uint64_t *out, uint64_t *sums, uint64_t *total,
+                       hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint32_t nblocks = (uint32_t)(n < kScanBlocks * 256ull ? (n + 255) / 256 : kScanBlocks);
+  const uint64_t seg = (n + nblocks - 1) / nblocks;
+  hipLaunchKernelGGL(k_scan_partial, dim3(nblocks), dim3(256), 0, stream, in, n, seg, sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, stream, sums, nblocks, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nblocks), dim3(256), 0, stream, in, n, seg, sums, out);
+  return hipGetLastError();
+}
+
+}  // namespace stimgpu

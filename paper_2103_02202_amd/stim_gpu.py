@@ -47,6 +47,7 @@ def lib():
         L.stim_frame_sample.argtypes = [vp, u64, u64, u64, vp, vp]
         L.stim_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.stim_batch_sample.argtypes = [ctypes.POINTER(StimRequest), ctypes.c_size_t, vp]
+        L.stim_format_shots.argtypes = [vp, u64, u64, ctypes.c_int, vp, u64, P64, vp]
         L.stim_kernel_timing.argtypes = [ctypes.c_int]
         L.stim_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P64]
         _lib = L
@@ -119,6 +120,31 @@ def stim_batch_sample(requests, stream=None):
         arr[i].out0 = r["out0"].data_ptr() if r.get("out0") is not None else None
         arr[i].out1 = r["out1"].data_ptr() if r.get("out1") is not None else None
     _check(lib().stim_batch_sample(arr, len(requests), _stream_ptr(stream)))
+
+
+STIM_FORMAT_01, STIM_FORMAT_B8, STIM_FORMAT_HITS, STIM_FORMAT_R8 = 0, 1, 2, 3
+FORMATS = {"01": STIM_FORMAT_01, "b8": STIM_FORMAT_B8, "hits": STIM_FORMAT_HITS, "r8": STIM_FORMAT_R8}
+
+
+def stim_format_shots(table, rows: int, num_shots: int, fmt, out=None, stream=None) -> int:
+    """Writes the shots of a [rows][W] device table in a shot-major format into
+    the uint8 device tensor `out` (or, with out=None, only returns the size).
+    Returns the byte length of the output."""
+    f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    n = ctypes.c_uint64()
+    cap = out.numel() if out is not None else 0
+    _check(lib().stim_format_shots(_dptr(table), rows, num_shots, f, _dptr(out), cap, ctypes.byref(n),
+                                   _stream_ptr(stream)))
+    return int(n.value)
+
+
+def format_shots(table, rows: int, num_shots: int, fmt, stream=None):
+    """Allocates the output and formats; returns a uint8 device tensor."""
+    import torch
+    n = stim_format_shots(table, rows, num_shots, fmt, None, stream)
+    out = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+    stim_format_shots(table, rows, num_shots, fmt, out, stream)
+    return out[:n]
 
 
 def stim_kernel_timing(enable: bool) -> None:
