@@ -548,9 +548,10 @@ void thresholds(double p, uint64_t t[64]) {
 }
 
 // The sequence of 64-bit draws used by noise on (instruction, slot, word).
-// Draw 0 takes its top 16 bits from a call shared by 16 consecutive slots and
-// its low 48 bits from lane 0 of the slot's own call; draws 1, 2, ... are the
-// following lanes of the slot's own calls.
+// Draw 0 takes its top 8 bits from a call shared by 32 consecutive slots
+// (byte slot % 32 of its 256 output bits, lane-major, least significant byte
+// first) and its low 56 bits from lane 0 of the slot's own call; draws 1, 2,
+// ... are the following lanes of the slot's own calls.
 struct NoiseDraws {
   uint64_t seed, instr, slot, word;
   uint64_t buf[4];
@@ -561,10 +562,10 @@ struct NoiseDraws {
     uint64_t d = buf[j & 3];
     if (j == 0) {
       uint64_t pre[4];
-      philox_call(seed, instr, slot >> 4, word, PURPOSE_NOISE_PREFIX << 32, pre);
-      uint64_t k = slot & 15;
-      uint64_t v = (pre[k >> 2] >> (16 * (k & 3))) & 0xFFFF;
-      d = (v << 48) | (d & ((1ull << 48) - 1));
+      philox_call(seed, instr, slot >> 5, word, PURPOSE_NOISE_PREFIX << 32, pre);
+      uint64_t k = slot & 31;
+      uint64_t v = (pre[k >> 3] >> (8 * (k & 7))) & 0xFF;
+      d = (v << 56) | (d & ((1ull << 56) - 1));
     }
     return d;
   }

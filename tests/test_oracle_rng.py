@@ -81,9 +81,9 @@ def python_hits(seed, instr, slot, word, p, K):
     blocks and exact thresholds."""
     key = [seed, oracle.key_hi()]
     t = exact_thresholds(p)
-    pre = numpy_philox_block([instr, slot >> 4, word, 2 << 32], key)
-    k = slot & 15
-    v = (pre[k >> 2] >> (16 * (k & 3))) & 0xFFFF
+    pre = numpy_philox_block([instr, slot >> 5, word, 2 << 32], key)
+    k = slot & 31
+    v = (pre[k >> 3] >> (8 * (k & 7))) & 0xFF
     draws = []
     j = 0
 
@@ -92,7 +92,7 @@ def python_hits(seed, instr, slot, word, p, K):
         blk = numpy_philox_block([instr, slot, word, (3 << 32) | (j >> 2)], key)
         d = blk[j & 3]
         if j == 0:
-            d = (v << 48) | (d & ((1 << 48) - 1))
+            d = (v << 56) | (d & ((1 << 56) - 1))
         j += 1
         return d
 
@@ -114,7 +114,7 @@ def python_hits(seed, instr, slot, word, p, K):
 
 @pytest.mark.parametrize("p,K", [(0.05, 0), (0.3, 3), (0.2, 15), (1.0, 0), (1.0, 15)])
 def test_hits_match_restatement(p, K):
-    for (instr, slot, word) in [(3, 0, 0), (7, 21, 5), (100, 1, 77), (9, 16, 2)]:
+    for (instr, slot, word) in [(3, 0, 0), (7, 21, 5), (100, 1, 77), (9, 16, 2), (4, 63, 1), (5, 32, 9)]:
         assert oracle.hits(11, instr, slot, word, p, K) == python_hits(11, instr, slot, word, p, K)
 
 
