@@ -272,8 +272,8 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   if (prepass) {
     for (size_t i = 0; i < ninst; i++) {
       const DevOp &op = P.ops[P.noise_pc[i]];
-      const uint64_t cut = P.thresholds[(size_t)op.aux * 64 + 63] >> 48;
-      const double q = (65536.0 - (double)cut) / 65536.0;
+      const uint64_t cut = P.thresholds[(size_t)op.aux * 64 + 63] >> 56;
+      const double q = (256.0 - (double)cut) / 256.0;
       const double mu = (double)op.n * cfg.tile_words * q;
       double capd = std::ceil(mu + 6.0 * std::sqrt(mu) + 16.0);
       uint32_t cap = capd > (double)kMaxTileRecords ? 0u : (uint32_t)capd;

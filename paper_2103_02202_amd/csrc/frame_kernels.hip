@@ -12,8 +12,8 @@
 // 16 n T bytes fit, otherwise in a global scratch buffer.
 //
 // Random bits are drawn cooperatively: a lane evaluates one Philox call for a
-// group of slots on one word -- four slots for Z randomisation, sixteen
-// 16-bit noise prefixes -- and only the few (slot, word) pairs whose prefix
+// group of slots on one word -- four slots for Z randomisation, thirty-two
+// 8-bit noise prefixes -- and only the few (slot, word) pairs whose prefix
 // admits an error are queued, compacted per wave in LDS, and expanded by all
 // lanes together (geometric gaps, Sec. 5.5).
 #include <hip/hip_runtime.h>
@@ -104,19 +104,19 @@ struct PhiloxCall {
   }
 };
 
-// Applies a noise op: prefix test per (16-slot group, word), wave-compacted
+// Applies a noise op: prefix test per (32-slot group, word), wave-compacted
 // expansion of the surviving (slot, word) pairs.
 template <int T, bool IN_LDS>
 __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                       uint32_t code, uint64_t instr, const uint64_t *thr) {
   const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const uint64_t cut = thr[63] >> 48;            // prefix below cut: no error in the word
+  const uint64_t cut = thr[63] >> 56;            // prefix below cut: no error in the word
   // 1 / log2(1 - p) from the exact value 2^64 - t[0] ~ p 2^64; seeds the gap search.
   const float p_est = (float)(0ull - thr[0]) * 0x1p-64f + (thr[0] == 0 ? 1.0f : 0.0f);
   const float inv_log2_keep = 1.0f / (log1pf(-p_est) * 1.44269504088896340736f);
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
-  const uint32_t g_lo = s_lo >> 4, ngroups = ((s_hi - 1) >> 4) - g_lo + 1;
+  const uint32_t g_lo = s_lo >> 5, ngroups = ((s_hi - 1) >> 5) - g_lo + 1;
   const uint32_t cand = ngroups * T;
   const uint32_t *tg = p.targets + op.toff;
   for (uint32_t base = wave * 64; base < cand; base += nwaves * 64) {
@@ -131,10 +131,10 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
       if (j < tl.valid) {
         r = philox_call(instr, g, p.word0 + tl.tw0 + j, PURPOSE_NOISE_PREFIX << 32, p.seed);
 #pragma unroll
-        for (uint32_t b = 0; b < 16; b++) {
-          uint32_t s = g * 16 + b;
-          uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
-          if (s >= s_lo && s < s_hi && v16 >= cut) mask |= 1u << b;
+        for (uint32_t b = 0; b < 32; b++) {
+          uint32_t s = g * 32 + b;
+          uint64_t vp = (r.v[b >> 3] >> (8 * (b & 7))) & 0xFF;
+          if (s >= s_lo && s < s_hi && vp >= cut) mask |= 1u << b;
         }
       }
     }
@@ -148,8 +148,8 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
         uint32_t b = (uint32_t)__builtin_ctz(m);
         m &= m - 1;
         if (idx >= r0 && idx < r0 + 64) {
-          uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
-          tl.queue[idx - r0] = ((uint64_t)(g * 16 + b) << 24) | ((uint64_t)j << 16) | v16;
+          uint64_t vp = (r.v[b >> 3] >> (8 * (b & 7))) & 0xFF;
+          tl.queue[idx - r0] = ((uint64_t)(g * 32 + b) << 24) | ((uint64_t)j << 16) | vp;
         }
         idx++;
       }
@@ -158,9 +158,9 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
         const uint64_t e = tl.queue[lane];
         const uint32_t s = (uint32_t)(e >> 24);
         const int jj = (int)((e >> 16) & 0xFF);
-        const uint64_t v16 = e & 0xFFFF;
+        const uint64_t vp = e & 0xFFFF;
         uint64_t mk[4] = {0, 0, 0, 0};
-        noise_masks(K, p.seed, instr, s, p.word0 + tl.tw0 + jj, thr, inv_log2_keep, v16, mk, PhiloxCall());
+        noise_masks(K, p.seed, instr, s, p.word0 + tl.tw0 + jj, thr, inv_log2_keep, vp, mk, PhiloxCall());
         const uint32_t k = s - s_lo;
         if (code == OP_NOISE_DEP2) {
           const uint32_t a = tg[2 * k], b = tg[2 * k + 1];
@@ -383,7 +383,7 @@ __device__ __forceinline__ void apply_records(const Tile<T, IN_LDS> &tl, uint32_
 }
 
 // Noise pre-pass: one workgroup per (noise execution, group of up to
-// kGenTiles tiles).  The prefix test runs over all (16-slot group, word)
+// kGenTiles tiles).  The prefix test runs over all (32-slot group, word)
 // candidates of the group's tiles, flattened so that the lanes stay busy;
 // surviving (slot, word) pairs are queued in LDS per tile and then expanded
 // into records, again flattened over the tiles.  If a tile's queue would
@@ -412,11 +412,11 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   if (threadIdx.x < 64) thr[threadIdx.x] = g.thresholds[(size_t)op.aux * 64 + threadIdx.x];
   if (threadIdx.x < S) { s_cnt[threadIdx.x] = 0; s_bad[threadIdx.x] = 0; }
   __syncthreads();
-  const uint64_t cut = thr[63] >> 48;
+  const uint64_t cut = thr[63] >> 56;
   const float p_est = (float)(0ull - thr[0]) * 0x1p-64f + (thr[0] == 0 ? 1.0f : 0.0f);
   const float inv_log2_keep = 1.0f / (log1pf(-p_est) * 1.44269504088896340736f);
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
-  const uint32_t g_lo = s_lo >> 4, ngroups = ((s_hi - 1) >> 4) - g_lo + 1;
+  const uint32_t g_lo = s_lo >> 5, ngroups = ((s_hi - 1) >> 5) - g_lo + 1;
   const uint32_t cand = ngroups * T;                 // candidates per tile
   const uint32_t qcap = cap < g.queue_per_tile ? cap : g.queue_per_tile;
   const uint32_t lane = threadIdx.x & 63;
@@ -432,10 +432,10 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
     if (c < all_cand && tw0 + j < g.num_words) {
       r = philox_call(instr, grp, g.word0 + tw0 + j, PURPOSE_NOISE_PREFIX << 32, g.seed);
 #pragma unroll
-      for (uint32_t b = 0; b < 16; b++) {
-        const uint32_t s = grp * 16 + b;
-        const uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
-        if (s >= s_lo && s < s_hi && v16 >= cut) mask |= 1u << b;
+      for (uint32_t b = 0; b < 32; b++) {
+        const uint32_t s = grp * 32 + b;
+        const uint64_t vp = (r.v[b >> 3] >> (8 * (b & 7))) & 0xFF;
+        if (s >= s_lo && s < s_hi && vp >= cut) mask |= 1u << b;
       }
     }
     // Queue positions: one LDS atomic per (wave, tile) present in the wave.
@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
       const uint32_t b = (uint32_t)__builtin_ctz(mask);
       mask &= mask - 1;
       if (idx < qcap) {
-        const uint64_t v16 = (r.v[b >> 2] >> (16 * (b & 3))) & 0xFFFF;
-        q[idx] = ((uint64_t)(grp * 16 + b - s_lo) << 24) | ((uint64_t)j << 16) | v16;
+        const uint64_t vp = (r.v[b >> 3] >> (8 * (b & 7))) & 0xFF;
+        q[idx] = ((uint64_t)(grp * 32 + b - s_lo) << 24) | ((uint64_t)j << 16) | vp;
       }
       idx++;
     }

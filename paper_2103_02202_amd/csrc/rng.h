@@ -6,7 +6,7 @@
 //
 // Counter layout for one random quantity:
 //   c0 = flat instruction index (all ones for the initial frame randomisation)
-//   c1 = target slot, or slot / 4 (Z randomisation), or slot / 16 (noise prefix)
+//   c1 = target slot, or slot / 4 (Z randomisation), or slot / 32 (noise prefix)
 //   c2 = absolute 64-shot word index (shot / 64)
 //   c3 = purpose << 32 | call number
 //
@@ -14,15 +14,15 @@
 // word) are lane slot % 4 of call (instr, slot / 4, word, 1 << 32).
 //
 // Pauli noise by geometric gaps (Sec. 5.5), per (instr, slot, word): a
-// sequence of 64-bit draws d_0, d_1, ...; d_0's top 16 bits are chunk slot % 16
-// (bits 16 (k % 4) .. of lane k / 4) of call (instr, slot / 16, word, 2 << 32)
-// and its low 48 bits come from lane 0 of call (instr, slot, word, 3 << 32);
+// sequence of 64-bit draws d_0, d_1, ...; d_0's top 8 bits are byte slot % 32
+// (bits 8 (k % 8) .. of lane k / 8) of call (instr, slot / 32, word, 2 << 32)
+// and its low 56 bits come from lane 0 of call (instr, slot, word, 3 << 32);
 // d_j (j >= 1) is lane j % 4 of call (instr, slot, word, 3 << 32 | j / 4).
 // Starting at position 0, each gap draw u advances the position by
 // G = #{g in 1..64 : u < t[g]}; a position below 64 is an error, followed (for
 // depolarizing channels) by a choice draw c = floor(u K / 2^64), then the
 // position steps past it.  Because the first draw's high bits come from a call
-// shared by 16 slots, most words are proved error-free without evaluating the
+// shared by 32 slots, most words are proved error-free without evaluating the
 // slot's own call.
 #pragma once
 
@@ -39,7 +39,9 @@ namespace stimgpu {
 constexpr uint64_t KEY_HI = 0x5354494D5F465241ull;
 constexpr uint64_t PURPOSE_ZRAND = 1, PURPOSE_NOISE_PREFIX = 2, PURPOSE_NOISE_DETAIL = 3;
 constexpr uint64_t INIT_INSTRUCTION = ~0ull;
-constexpr uint64_t MASK48 = (1ull << 48) - 1;
+constexpr uint64_t MASK56 = (1ull << 56) - 1;
+// Slots sharing one noise-prefix call, and the width of each slot's prefix.
+constexpr uint32_t PREFIX_SLOTS = 32, PREFIX_BITS = 8;
 
 struct U64x4 { uint64_t v[4]; };
 
@@ -94,10 +96,10 @@ STIM_HD uint64_t zrand_word(uint64_t seed, uint64_t instr, uint64_t slot, uint64
   return lane_of(r, (uint32_t)(slot & 3));
 }
 
-STIM_HD uint64_t noise_prefix16(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word) {
-  U64x4 r = philox4x64_10(instr, slot >> 4, word, PURPOSE_NOISE_PREFIX << 32, seed, KEY_HI);
-  uint32_t k = (uint32_t)(slot & 15);
-  return (lane_of(r, k >> 2) >> (16 * (k & 3))) & 0xFFFF;
+STIM_HD uint64_t noise_prefix(uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word) {
+  U64x4 r = philox4x64_10(instr, slot >> 5, word, PURPOSE_NOISE_PREFIX << 32, seed, KEY_HI);
+  uint32_t k = (uint32_t)(slot & 31);
+  return (lane_of(r, k >> 3) >> (8 * (k & 7))) & 0xFF;
 }
 
 // G = #{g in 1..64 : u < t[g-1]} for non-increasing t.
@@ -126,13 +128,13 @@ STIM_HD int gap_length_from_guess(uint64_t u, const uint64_t *t, float inv_log2_
 // Walks the errors of one noise site on one word (geometric gaps, Sec. 5.5):
 // calls on_hit(position, choice) for each error in increasing position
 // (choice = floor(u K / 2^64) from the draw after the gap, K = 0: no choice).
-// philox(c0, c1, c2, c3, seed) evaluates one generator call; v16 is the
-// site's 16-bit prefix; inv_log2_keep = 1 / log2(1 - p) seeds the gap search.
+// philox(c0, c1, c2, c3, seed) evaluates one generator call; vp is the
+// site's 8-bit prefix; inv_log2_keep = 1 / log2(1 - p) seeds the gap search.
 // With max_draws set, the walk stops (returning false) instead of taking draw
 // number max_draws; errors reported before that point are then incomplete.
 template <typename Philox, typename OnHit>
 STIM_HD bool noise_walk(int K, uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
-                        float inv_log2_keep, uint64_t v16, Philox philox, OnHit on_hit,
+                        float inv_log2_keep, uint64_t vp, Philox philox, OnHit on_hit,
                         uint32_t max_draws = 0xFFFFFFFFu) {
   // Four draws per call, kept in named registers (no indexed local array).
   uint64_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
@@ -146,7 +148,7 @@ STIM_HD bool noise_walk(int K, uint64_t seed, uint64_t instr, uint64_t slot, uin
     j++;
     return lane == 0 ? b0 : lane == 1 ? b1 : lane == 2 ? b2 : b3;
   };
-  uint64_t u = (v16 << 48) | (draw() & MASK48);
+  uint64_t u = (vp << 56) | (draw() & MASK56);
   int pos = 0;
   while (true) {
     pos += gap_length_from_guess(u, t, inv_log2_keep);
@@ -183,8 +185,8 @@ STIM_HD void add_error(int K, int pos, uint32_t c, uint64_t m[4]) {
 // Error masks of one noise site on one word (see add_error for m).
 template <typename Philox>
 STIM_HD void noise_masks(int K, uint64_t seed, uint64_t instr, uint64_t slot, uint64_t word, const uint64_t *t,
-                         float inv_log2_keep, uint64_t v16, uint64_t m[4], Philox philox) {
-  noise_walk(K, seed, instr, slot, word, t, inv_log2_keep, v16, philox,
+                         float inv_log2_keep, uint64_t vp, uint64_t m[4], Philox philox) {
+  noise_walk(K, seed, instr, slot, word, t, inv_log2_keep, vp, philox,
              [&](int pos, uint32_t c) { add_error(K, pos, c, m); });
 }
 
