@@ -128,8 +128,8 @@ bool fits_lds(uint64_t n, int T) {
 
 // Picks the shot-tile width and frame placement: the widest tile whose frame
 // slice fits in LDS while still giving enough tiles to occupy the GPU.
-// STIM_TILE_WORDS (1..32, power of two) and STIM_FRAME_PLACEMENT (lds|global)
-// override the choice; results do not depend on it.
+// STIM_TILE_WORDS (1..32, power of two), STIM_FRAME_PLACEMENT (lds|global)
+// and STIM_FRAME_THREADS override the choice; results do not depend on it.
 FrameConfig choose_config(uint64_t n, uint64_t W) {
   FrameConfig cfg{1, true, 256};
   const char *tw = std::getenv("STIM_TILE_WORDS"), *pl = std::getenv("STIM_FRAME_PLACEMENT");
@@ -141,6 +141,11 @@ FrameConfig choose_config(uint64_t n, uint64_t W) {
     cfg.tile_words = T;
     cfg.in_lds = lds;
     cfg.threads = lds ? threads_for((size_t)16 * n * T) : 256;
+    if (const char *th = std::getenv("STIM_FRAME_THREADS")) {
+      const int t = std::atoi(th);
+      if (t >= 64 && t <= 1024 && t % 64 == 0 && frame_lds_bytes(n, T, lds, (uint32_t)t) <= kMaxLdsBytes)
+        cfg.threads = (uint32_t)t;
+    }
     return cfg;
   }
   const int widths[] = {32, 16, 8, 4, 2, 1};
@@ -264,7 +269,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   bool prepass = ninst > 0 && !(pre_env && std::strcmp(pre_env, "0") == 0) && ntiles <= 0x7FFFFFFFull &&
                  P.num_qubits < (1ull << 27);                    // records hold 27-bit qubit indices
   // Reservations above this many records per (execution, tile) stay inline.
-  const uint32_t kMaxTileRecords = kGenQueue / 2;
+  const uint32_t kMaxTileRecords = kGenQueue;
   std::vector<uint64_t> nbase(ninst);
   std::vector<uint32_t> ncap(ninst);
   uint64_t nrec = 0;

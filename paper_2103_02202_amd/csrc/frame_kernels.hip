@@ -7,9 +7,10 @@
 // splits instructions where a qubit repeats), so they run in parallel, and a
 // barrier separates consecutive ops.
 //
-// The frame slice of a tile is two bit planes, X then Z, each [n][T] uint64
-// (bit j of word w = shot 64 (tile word w) + j).  It lives in LDS when
-// 16 n T bytes fit, otherwise in a global scratch buffer.
+// The frame slice of a tile holds T X words and T Z words per qubit (bit j of
+// word w = shot 64 (tile word w) + j).  It lives in LDS when 16 n T bytes
+// fit, as two planes X then Z, each [n][T]; otherwise in a global scratch
+// buffer as [n][2][T] (a qubit's X and Z words adjacent).
 //
 // Random bits are drawn cooperatively: a lane evaluates one Philox call for a
 // group of slots on one word -- four slots for Z randomisation, thirty-two
@@ -88,7 +89,7 @@ struct Tile {
 
   __device__ __forceinline__ Index at(uint32_t q, int j) const {
     if constexpr (IN_LDS) return q * (uint32_t)T + (uint32_t)j;
-    else return (size_t)q * T + j;
+    else return (size_t)q * (2 * T) + j;
   }
 };
 
@@ -526,7 +527,10 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   if constexpr (IN_LDS) F = lds + nwaves * 64 + 64;
   else F = p.scratch + (size_t)tile * 2 * n * T;
   tl.FX = F;
-  tl.FZ = F + (size_t)n * T;
+  // In LDS the X and Z planes are separate (fewer bank conflicts on the
+  // strided target patterns); in global memory each qubit's X and Z words
+  // are adjacent, so one cache line serves both.
+  tl.FZ = IN_LDS ? F + (size_t)n * T : F + T;
   tl.tw0 = (uint64_t)tile * T;
   tl.valid = (int)((p.num_words - tl.tw0) < (uint64_t)T ? (p.num_words - tl.tw0) : (uint64_t)T);
 
