@@ -159,11 +159,13 @@ FrameConfig choose_config(uint64_t n, uint64_t W) {
     }
   }
   if (fits_lds(n, 1)) return cfg;
-  // Frame slice too large for LDS even for one word: global scratch.  Two
-  // words per tile measured fastest (wider tiles leave too few workgroups).
+  // Frame slice too large for LDS even for one word: global scratch.  Wider
+  // tiles make each frame access a longer contiguous piece; measured at
+  // d = 101: 8 words per tile once there are at least 256 tiles of them, else
+  // 4, else 2 (512 threads; about one workgroup per CU in flight).
   cfg.in_lds = false;
-  cfg.threads = 256;
-  cfg.tile_words = W >= 1024 ? 2 : 1;
+  cfg.threads = 512;
+  cfg.tile_words = W >= 2048 ? 8 : W >= 1024 ? 4 : W >= 128 ? 2 : 1;
   return cfg;
 }
 
@@ -236,6 +238,20 @@ void release_timing() {
     (void)hipEventDestroy(t.end);
   }
   g_timing.clear();
+}
+
+// Compute units of a device (cached; callers may be on several host threads).
+std::mutex g_cu_mu;
+std::map<int, int> g_cu_count;
+int cu_count(int dev) {
+  std::lock_guard<std::mutex> lock(g_cu_mu);
+  auto it = g_cu_count.find(dev);
+  if (it != g_cu_count.end()) return it->second;
+  hipDeviceProp_t prop;
+  int n = 256;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) n = prop.multiProcessorCount;
+  g_cu_count[dev] = n;
+  return n;
 }
 
 // Runs the frame kernel; ref == nullptr writes raw flips.
@@ -375,7 +391,14 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     p.noise_instances = (uint32_t)ninst;
   }
   if (!cfg.in_lds) {
-    uint64_t tiles = ntiles;
+    // One scratch slot per workgroup in flight: about one workgroup per CU, so
+    // that the frames in flight stay within the last-level cache.
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    uint64_t slots = (uint64_t)cu_count(dev);
+    if (const char *v = std::getenv("STIM_FRAME_SLOTS")) slots = std::max<long>(1, atol(v));
+    cfg.slots = (uint32_t)std::min<uint64_t>(slots, ntiles);
+    const uint64_t tiles = cfg.slots;
     size_t bytes = (size_t)tiles * cfg.tile_words * 16 * std::max<uint64_t>(c->prog.num_qubits, 1);
     if ((e = hipMallocAsync((void **)&p.scratch, bytes, s)) != hipSuccess) {
       free_prepass();
@@ -434,7 +457,6 @@ struct BatchPlan {
 std::mutex g_batch_mu;
 std::vector<std::unique_ptr<BatchPlan>> g_plans;           // most recent last
 std::map<std::string, FrameConfig> g_tuned;                // shape class -> config
-std::map<int, int> g_cu_count;
 std::vector<uint64_t> g_seen;                               // signatures of recent one-shot request sets
 
 void free_plan(BatchPlan *pl) {
@@ -463,15 +485,6 @@ bool same_request(const stim_request &a, const stim_request &b) {
          a.mode == b.mode && a.out0 == b.out0 && a.out1 == b.out1;
 }
 
-int cu_count(int dev) {
-  auto it = g_cu_count.find(dev);
-  if (it != g_cu_count.end()) return it->second;
-  hipDeviceProp_t prop;
-  int n = 256;
-  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) n = prop.multiProcessorCount;
-  g_cu_count[dev] = n;
-  return n;
-}
 
 bool batch_fits(uint64_t n, int T, uint32_t threads) {
   return frame_lds_bytes(n, T, true, threads) + kBatchStaticLds <= kMaxLdsBytes;

@@ -64,6 +64,7 @@ struct FrameConfig {
   int tile_words;               // T: 1, 2, 4, 8, 16 or 32
   bool in_lds;
   uint32_t threads;
+  uint32_t slots = 0;           // global frame: workgroups (and scratch slots); 0 = one per tile
 };
 
 // LDS available to one workgroup on gfx950.

@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
 // LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
 template <int T, bool IN_LDS>
-__device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, uint64_t *lds) {
+__device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, uint32_t slot, uint64_t *lds) {
   const uint32_t nwaves = blockDim.x >> 6;
   const uint32_t n = p.num_qubits;
   Tile<T, IN_LDS> tl;
@@ -525,7 +525,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint32_t thr_row = 0xFFFFFFFFu;
   uint64_t *F;
   if constexpr (IN_LDS) F = lds + nwaves * 64 + 64;
-  else F = p.scratch + (size_t)tile * 2 * n * T;
+  else F = p.scratch + (size_t)slot * 2 * n * T;
   tl.FX = F;
   // In LDS the X and Z planes are separate (fewer bank conflicts on the
   // strided target patterns); in global memory each qubit's X and Z words
@@ -630,10 +630,15 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   }
 }
 
+// One workgroup per tile, or (a global frame) a smaller grid of workgroups
+// that take tiles in turn, each reusing its own scratch slot, so that the
+// frames in flight stay within the caches.
 template <int T, bool IN_LDS>
 __global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
   extern __shared__ uint64_t lds[];
-  walk_tile<T, IN_LDS>(p, xcd_tile(blockIdx.x, gridDim.x), lds);
+  const uint32_t ntiles = (uint32_t)((p.num_words + T - 1) / T);
+  const uint32_t first = xcd_tile(blockIdx.x, gridDim.x);
+  for (uint32_t t = first; t < ntiles; t += gridDim.x) walk_tile<T, IN_LDS>(p, t, blockIdx.x, lds);
 }
 
 // Persistent multi-circuit kernel: every workgroup pops (request, tile) items
@@ -653,7 +658,7 @@ __global__ void __launch_bounds__(1024) k_batch(const FrameParams *__restrict__ 
     if (it >= num_items) break;                  // uniform: every wave leaves together
     const BatchItem bi = items[it];
     const FrameParams p = reqs[bi.req];
-    walk_tile<T, true>(p, bi.tile, lds);
+    walk_tile<T, true>(p, bi.tile, 0, lds);
   }
 }
 
@@ -725,6 +730,7 @@ hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_
   size_t lds = frame_lds_bytes(p.num_qubits, cfg.tile_words, cfg.in_lds, cfg.threads);
   if (lds > kMaxLdsBytes || cfg.threads % 64 || cfg.threads == 0 || cfg.threads > 1024) return hipErrorInvalidValue;
   uint32_t tiles = (uint32_t)((p.num_words + cfg.tile_words - 1) / cfg.tile_words);
+  if (!cfg.in_lds && cfg.slots && cfg.slots < tiles) tiles = cfg.slots;      // workgroups of a global frame
 #define STIM_CASE(TT)                                                                        \
   case TT:                                                                                   \
     return cfg.in_lds ? launch_frame_t<TT, true>(p, tiles, cfg.threads, lds, stream)         \

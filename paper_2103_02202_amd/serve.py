@@ -34,6 +34,7 @@ from concurrent.futures import ThreadPoolExecutor
 from . import stim_gpu
 
 LDS_FRAME_LIMIT_QUBITS = 9600       # beyond this the frame slice lives in a global scratch buffer
+GLOBAL_FRAME_WORDS = 256 * 8         # at most this many words of global frame in flight (workgroups x tile words)
 
 
 class PoolCircuit:
@@ -47,7 +48,7 @@ class PoolCircuit:
         c = self.c
         b = 8 * W * (c.num_detectors + max(c.num_observables, 1) + max(c.num_measurements, 1))
         if c.num_qubits > LDS_FRAME_LIMIT_QUBITS:
-            b += 16 * W * c.num_qubits
+            b += 16 * min(W, GLOBAL_FRAME_WORDS) * c.num_qubits
         return b
 
 
