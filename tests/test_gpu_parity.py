@@ -211,3 +211,18 @@ def test_kernel_timing_counts_passes_and_keeps_results(sg):
     finally:
         sg.stim_kernel_timing(False)
     assert (timed == base).all()
+
+
+@pytest.mark.parametrize("tile,slots,threads", [(1, 3, "256"), (2, 2, "512"), (4, 1, "1024")])
+def test_global_frame_workgroups_take_tiles_in_turn(sg, tile, slots, threads, monkeypatch):
+    """A global frame walked by fewer workgroups than tiles: each workgroup
+    reuses its scratch slot for several tiles."""
+    text = wl.surface_code(5, 4, 2e-2)
+    shots = 64 * 23 + 5
+    announce("global slots", tile, slots, threads, shots)
+    monkeypatch.setenv("STIM_TILE_WORDS", str(tile))
+    monkeypatch.setenv("STIM_FRAME_PLACEMENT", "global")
+    monkeypatch.setenv("STIM_FRAME_SLOTS", str(slots))
+    monkeypatch.setenv("STIM_FRAME_THREADS", threads)
+    check_meas(sg, text, 21, shots)
+    check_det(sg, text, 21, shots)
