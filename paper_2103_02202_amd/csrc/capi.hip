@@ -78,10 +78,29 @@ int ensure_reference(stim_circuit *c) {
 }
 
 // Uploads the program and reference to the current device (first use only).
+// The per-call scratch (flip record, noise records, frame slots) comes from
+// the device's stream-ordered pool.  Its memory is kept reserved between
+// calls instead of being returned at every synchronisation, so that a steady
+// stream of calls does not map and unmap gigabytes each time.
+std::mutex g_pool_mu;
+std::vector<int> g_pool_ready;
+
+void keep_pool_reserved(int dev) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (std::find(g_pool_ready.begin(), g_pool_ready.end(), dev) != g_pool_ready.end()) return;
+  g_pool_ready.push_back(dev);
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t keep = ~0ull;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+}
+
 int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  keep_pool_reserved(dev);
   auto it = c->dev.find(dev);
   if (it != c->dev.end()) {
     *out = &it->second;

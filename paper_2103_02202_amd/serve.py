@@ -13,11 +13,13 @@ as they arrive:
   ``max_chunk_shots`` shots and ``max_chunk_bytes`` of footprint (results are
   identical because random bits are keyed by absolute shot); the request
   completes with its last chunk.
-* Continuous batching: whenever a launch slot (a HIP stream) is free, every
-  admitted chunk that has arrived is submitted together as one persistent
-  batched launch (stim_batch_sample) on that slot.  Chunks that arrive while
-  others run start on the next free slot, so their work overlaps on the
-  device.
+* Continuous batching: whenever a launch slot (a HIP stream) is free, the
+  admitted small chunks that have arrived are submitted together as one
+  persistent batched launch (stim_batch_sample) on that slot.  Chunks that
+  arrive while others run start on the next free slot, so their work overlaps
+  on the device.  Big chunks (at least ``big_work`` shot-gates) take slot 0
+  one at a time: a large circuit's frames fill the GPU and its last-level
+  cache on their own, and two of them side by side only slow each other down.
 * Latency: arrival (the request's scheduled Poisson time) to the completion of
   its last chunk, observed by polling HIP events; p50 / p99 reported beside
   throughput.
@@ -71,7 +73,7 @@ def percentile(values, q):
 class Server:
     def __init__(self, pool, hbm_budget_bytes: int = 48 << 30, num_slots: int = 4,
                  max_chunk_shots: int = 1 << 18, max_chunk_bytes: int | None = None, max_group: int = 64,
-                 max_group_shot_gates: float = 4e10, keep_outputs: bool = False):
+                 max_group_shot_gates: float = 4e10, keep_outputs: bool = False, big_work: float = 1e11):
         import torch
         self.torch = torch
         self.pool = pool
@@ -82,6 +84,7 @@ class Server:
         self.max_group = max_group
         self.max_group_work = max_group_shot_gates
         self.keep_outputs = keep_outputs
+        self.big_work = big_work
 
     # -- chunks -------------------------------------------------------------
     def _chunks(self, req):
@@ -158,26 +161,48 @@ class Server:
                 else:
                     still.append((slot, ev, chs, nbytes))
             inflight = still
-            # admissions: one group per free slot, FIFO, bounded in work so
-            # that a launch stays short and later arrivals start soon
+            # admissions: big chunks one at a time on slot 0; small chunks in
+            # groups on the other slots, FIFO, bounded in work so that a
+            # launch stays short and later arrivals start soon
             while free_slots and pending:
+                bigs = [ch for ch in pending if ch["work"] >= self.big_work]
+                smalls = [ch for ch in pending if ch["work"] < self.big_work]
+                small_slots = [x for x in free_slots if x != 0]
+                if 0 in free_slots and not bigs:
+                    small_slots.append(0)            # no big chunk waiting: slot 0 takes small ones too
+                if len(self.slots) == 1:
+                    slot, queue = 0, list(pending)
+                elif 0 in free_slots and bigs:
+                    slot, queue = 0, bigs
+                elif smalls and small_slots:
+                    slot, queue = small_slots[0], smalls
+                else:
+                    break
+                big_slot = queue[0]["work"] >= self.big_work
+                if big_slot:
+                    limit_n, limit_w = 1, float("inf")
+                else:
+                    limit_n, limit_w = self.max_group, self.max_group_work
                 group, gbytes, gwork = [], 0, 0.0
-                while (pending and len(group) < self.max_group and used + gbytes + pending[0]["bytes"] <= self.budget
-                       and (not group or gwork + pending[0]["work"] <= self.max_group_work)):
-                    ch = pending.pop(0)
+                while (queue and len(group) < limit_n and used + gbytes + queue[0]["bytes"] <= self.budget
+                       and (not group or gwork + queue[0]["work"] <= limit_w)
+                       and (queue[0]["work"] >= self.big_work) == big_slot):
+                    ch = queue.pop(0)
                     group.append(ch)
                     gbytes += ch["bytes"]
                     gwork += ch["work"]
                 if not group:
                     if not inflight:         # a chunk larger than the whole budget: run it alone
-                        group = [pending.pop(0)]
+                        group = [queue.pop(0)]
                         gbytes = group[0]["bytes"]
                     else:
-                        if not pending[0]["deferred"]:
-                            pending[0]["deferred"] = True
+                        if not queue[0]["deferred"]:
+                            queue[0]["deferred"] = True
                             stats["deferrals"] += 1
                         break
-                slot = free_slots.pop(0)
+                taken = {id(ch) for ch in group}
+                pending = [ch for ch in pending if id(ch) not in taken]
+                free_slots.remove(slot)
                 stream = self.slots[slot]
                 with torch.cuda.stream(stream):
                     for ch in group:
