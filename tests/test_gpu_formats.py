@@ -28,6 +28,8 @@ def sg():
 
 def random_table(rng, rows, shots, density):
     W = (shots + 63) // 64
+    if rows == 0:
+        return np.zeros((0, W), dtype=np.uint64)
     bits = rng.random((rows, W * 64)) < density
     bits[:, shots:] = False                     # tail bits of the last word are zero, as the samplers write
     words = np.packbits(bits.reshape(rows, W, 64), axis=2, bitorder="little").view(np.uint64).reshape(rows, W)
@@ -47,7 +49,7 @@ def check(sg, words, rows, shots, fmt):
 
 
 @pytest.mark.parametrize("fmt", ["01", "b8", "hits", "r8"])
-@pytest.mark.parametrize("rows,shots,density", [(1, 1, 0.5), (7, 70, 0.5), (64, 64, 0.3), (65, 200, 0.1),
+@pytest.mark.parametrize("rows,shots,density", [(0, 5, 0.0), (1, 1, 0.5), (7, 70, 0.5), (64, 64, 0.3), (65, 200, 0.1),
                                                 (130, 1000, 0.02), (300, 777, 0.001), (600, 129, 0.0),
                                                 (1000, 300, 1.0), (70, 3000, 0.05)])
 def test_random_tables(sg, fmt, rows, shots, density):
