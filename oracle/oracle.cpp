@@ -32,6 +32,13 @@
 //     word, purpose).  See philox_* and the noise / ZRAND helpers below.
 //   - DEPOLARIZE1(p): X, Y, Z each with p/3.  DEPOLARIZE2(p): each of the 15
 //     non-identity two-qubit Paulis with p/15.
+//   - Classically controlled Paulis (Sec. 3, "Tracking Corrections"): CX, CY
+//     and CZ take a measurement-record target rec[-k] in place of the control
+//     (CZ on either side); the Pauli X, Y or Z is applied to the qubit when
+//     that measurement's result is 1.  The reference run applies it when the
+//     reference result is 1, the frame takes the rest: P^(result) =
+//     P^(reference) P^(flip), so the frame is multiplied by P where the
+//     measurement was flipped.
 
 #include <cstdint>
 #include <cstring>
@@ -133,8 +140,13 @@ struct Instr {
   double p = 0;                 // noise probability (noise channels)
   std::vector<uint32_t> q;      // qubit targets
   std::vector<uint64_t> rec;    // absolute measurement indices (DETECTOR/OBSERVABLE)
+  // CX/CY/CZ: per target, the absolute index of a measurement-record target
+  // (classical control), or NO_REC for a qubit.
+  std::vector<uint64_t> ctl;
   uint64_t obs = 0;             // observable index
 };
+
+const uint64_t NO_REC = ~0ull;
 
 struct Circuit {
   std::vector<Instr> ops;       // unrolled
@@ -243,6 +255,36 @@ void parse_lines(const std::vector<std::string> &lines, size_t &i, std::vector<N
   if (in_block) throw ParseError{(int)lines.size(), "unterminated REPEAT block"};
 }
 
+bool is_rec(const std::string &t) {
+  std::string u = upper(t);
+  return u.size() >= 7 && u.compare(0, 5, "REC[-") == 0 && u.back() == ']';
+}
+
+// Absolute measurement index of a rec[-k] target, k measurements back.
+uint64_t rec_index(const std::string &t, uint64_t num_meas, int line) {
+  std::string u = upper(t);
+  uint64_t k;
+  if (!parse_u64(u.substr(5, u.size() - 6), k) || k == 0) throw ParseError{line, "bad lookback"};
+  if (k > num_meas) throw ParseError{line, "lookback reaches before the first measurement"};
+  return num_meas - k;
+}
+
+// A classically controlled pair of a CX/CY/CZ instruction: the qubit it acts
+// on, the controlling measurement and the Pauli (bit 0: X part, bit 1: Z
+// part).  Returns false for an ordinary two-qubit pair.
+bool controlled_pair(const Instr &ins, size_t k, uint32_t &q, uint64_t &m, int &pauli) {
+  if (ins.ctl.empty()) return false;
+  const bool ra = ins.ctl[k] != NO_REC, rb = ins.ctl[k + 1] != NO_REC;
+  if (!ra && !rb) return false;
+  q = ra ? ins.q[k + 1] : ins.q[k];
+  m = ra ? ins.ctl[k] : ins.ctl[k + 1];
+  const std::string name = GATES[ins.gate].name;
+  pauli = name == "CX" ? 1 : name == "CZ" ? 2 : 3;
+  return true;
+}
+
+const char *pauli_gate_name(int pauli) { return pauli == 1 ? "X" : pauli == 2 ? "Z" : "Y"; }
+
 // Walks the tree and appends unrolled instructions.
 void unroll(const std::vector<Node> &nodes, Circuit &c) {
   for (const Node &n : nodes) {
@@ -268,13 +310,8 @@ void unroll(const std::vector<Node> &nodes, Circuit &c) {
     }
     if (g.kind == K_DETECTOR || g.kind == K_OBSERVABLE) {
       for (const std::string &t : n.targets) {
-        std::string u = upper(t);
-        if (u.size() < 7 || u.compare(0, 5, "REC[-") != 0 || u.back() != ']')
-          throw ParseError{n.line, "expected rec[-k] target, got '" + t + "'"};
-        uint64_t k;
-        if (!parse_u64(u.substr(5, u.size() - 6), k) || k == 0) throw ParseError{n.line, "bad lookback"};
-        if (k > c.num_meas) throw ParseError{n.line, "lookback reaches before the first measurement"};
-        ins.rec.push_back(c.num_meas - k);
+        if (!is_rec(t)) throw ParseError{n.line, "expected rec[-k] target, got '" + t + "'"};
+        ins.rec.push_back(rec_index(t, c.num_meas, n.line));
       }
       if (g.kind == K_DETECTOR) {
         c.detectors.push_back(ins.rec);
@@ -284,17 +321,31 @@ void unroll(const std::vector<Node> &nodes, Circuit &c) {
         for (uint64_t m : ins.rec) c.observables[ins.obs].push_back(m);
       }
     } else if (g.kind != K_ANNOTATION) {
-      for (const std::string &t : n.targets) {
+      const std::string gname = g.name;
+      const bool controllable = gname == "CX" || gname == "CY" || gname == "CZ";
+      for (size_t k = 0; k < n.targets.size(); k++) {
+        const std::string &t = n.targets[k];
+        if (controllable && is_rec(t)) {
+          // The record may replace the control (CZ: either qubit), not both.
+          if (k % 2 == 1 && gname != "CZ") throw ParseError{n.line, "a record target must be the control"};
+          ins.q.push_back(0);
+          ins.ctl.push_back(rec_index(t, c.num_meas, n.line));
+          continue;
+        }
         uint64_t v;
         if (!parse_u64(t, v) || v >= (1ull << 31)) throw ParseError{n.line, "bad qubit target '" + t + "'"};
         ins.q.push_back((uint32_t)v);
+        ins.ctl.push_back(NO_REC);
         if (v + 1 > c.num_qubits) c.num_qubits = v + 1;
       }
       if ((g.kind == K_CLIFFORD2 || g.kind == K_NOISE2) && ins.q.size() % 2 != 0)
         throw ParseError{n.line, "two-qubit operation needs an even number of targets"};
       if (g.kind == K_CLIFFORD2 || g.kind == K_NOISE2)
-        for (size_t k = 0; k < ins.q.size(); k += 2)
-          if (ins.q[k] == ins.q[k + 1]) throw ParseError{n.line, "two-qubit operation on one qubit"};
+        for (size_t k = 0; k < ins.q.size(); k += 2) {
+          const bool ra = ins.ctl[k] != NO_REC, rb = ins.ctl[k + 1] != NO_REC;
+          if (ra && rb) throw ParseError{n.line, "both targets are measurement records"};
+          if (!ra && !rb && ins.q[k] == ins.q[k + 1]) throw ParseError{n.line, "two-qubit operation on one qubit"};
+        }
       if (g.kind == K_MEASURE || g.kind == K_MEASURE_RESET) c.num_meas += ins.q.size();
       if (g.kind == K_CLIFFORD1 || g.kind == K_RESET || g.kind == K_MEASURE || g.kind == K_MEASURE_RESET)
         c.num_gate_targets += ins.q.size();
@@ -610,7 +661,16 @@ std::vector<uint8_t> reference(const Circuit &c, bool canonical, uint64_t coin_s
         for (uint32_t q : ins.q) t.prepend(ins.gate, {q});
         break;
       case K_CLIFFORD2:
-        for (size_t k = 0; k < ins.q.size(); k += 2) t.prepend(ins.gate, {ins.q[k], ins.q[k + 1]});
+        for (size_t k = 0; k < ins.q.size(); k += 2) {
+          uint32_t q;
+          uint64_t m;
+          int pauli;
+          if (controlled_pair(ins, k, q, m, pauli)) {
+            if (ref[m]) t.prepend(find_gate(pauli_gate_name(pauli)), {q});   // the reference's own result
+          } else {
+            t.prepend(ins.gate, {ins.q[k], ins.q[k + 1]});
+          }
+        }
         break;
       case K_MEASURE:
       case K_MEASURE_RESET:
@@ -672,6 +732,16 @@ void simulate_word(const Circuit &c, const std::vector<uint8_t> &ref, const std:
       case K_CLIFFORD2: {
         const FrameRule &r = rules[ins.gate];
         for (size_t s = 0; s < ins.q.size(); s += r.k) {
+          uint32_t fq;
+          uint64_t fm;
+          int pauli;
+          if (r.k == 2 && controlled_pair(ins, s, fq, fm, pauli)) {
+            // Shots whose controlling result differs from the reference's get
+            // the Pauli in their frame.
+            if (pauli & 1) x[fq] ^= flips[fm];
+            if (pauli & 2) z[fq] ^= flips[fm];
+            continue;
+          }
           uint64_t in[4] = {0, 0, 0, 0}, out[4] = {0, 0, 0, 0};
           for (int t = 0; t < r.k; t++) { in[2 * t] = x[ins.q[s + t]]; in[2 * t + 1] = z[ins.q[s + t]]; }
           for (int gen = 0; gen < 2 * r.k; gen++)
@@ -950,14 +1020,25 @@ int oracle_z_image(void *hv, uint32_t q, char *out, size_t cap) {
   try {
     const Circuit &c = ((Handle *)hv)->c;
     Tableau t(c.num_qubits);
+    std::vector<int> results;
     for (const Instr &ins : c.ops) {
       const GateInfo &g = GATES[ins.gate];
       if (g.kind == K_CLIFFORD1) for (uint32_t qq : ins.q) t.prepend(ins.gate, {qq});
       if (g.kind == K_CLIFFORD2)
-        for (size_t k = 0; k < ins.q.size(); k += 2) t.prepend(ins.gate, {ins.q[k], ins.q[k + 1]});
+        for (size_t k = 0; k < ins.q.size(); k += 2) {
+          uint32_t fq;
+          uint64_t fm;
+          int pauli;
+          if (controlled_pair(ins, k, fq, fm, pauli)) {
+            if (results[fm]) t.prepend(find_gate(pauli_gate_name(pauli)), {fq});
+          } else {
+            t.prepend(ins.gate, {ins.q[k], ins.q[k + 1]});
+          }
+        }
       if (g.kind == K_MEASURE || g.kind == K_MEASURE_RESET || g.kind == K_RESET)
         for (uint32_t qq : ins.q) {
-          t.measure(qq, 0);
+          int r = t.measure(qq, 0);
+          if (g.kind != K_RESET) results.push_back(r);
           if (g.kind != K_MEASURE) t.zs[qq].sign = 0;
         }
     }

@@ -25,6 +25,7 @@ ALIASES = {"H_XZ": "H", "SQRT_Z": "S", "SQRT_Z_DAG": "S_DAG", "CNOT": "CX", "ZCX
            "ZCY": "CY", "ZCZ": "CZ", "RZ": "R", "MZ": "M", "MRZ": "MR"}
 TWO_QUBIT = {"CX", "CY", "CZ", "SWAP", "DEPOLARIZE2"}
 NOISE = {"X_ERROR", "Y_ERROR", "Z_ERROR", "DEPOLARIZE1", "DEPOLARIZE2"}
+CONTROLLED_PAULI = {"CX": "X", "CY": "Y", "CZ": "Z"}
 
 
 def parse(text: str):
@@ -54,10 +55,9 @@ def parse(text: str):
                 out.extend(body * reps)
                 continue
             toks = rest.split()
-            if name in ("DETECTOR", "OBSERVABLE_INCLUDE"):
-                targets = [-int(t[5:-1]) for t in toks]
-            else:
-                targets = [int(t) for t in toks]
+            # rec[-k] becomes -k: detector terms, or the classical control of
+            # CX / CY / CZ.
+            targets = [-int(t[5:-1]) if t.lower().startswith("rec[") else int(t) for t in toks]
             val = float(arg.split(",")[0]) if arg and name in NOISE else None
             out.append((name, val, targets))
         return out
@@ -116,7 +116,17 @@ def _run(ops, n, outcome_fn, paulis=None):
         if name in UNITARIES:
             k = 2 if name in TWO_QUBIT else 1
             for s in range(0, len(t), k):
-                st.apply(UNITARIES[name], t[s:s + k])
+                pair = t[s:s + k]
+                if k == 2 and min(pair) < 0:
+                    # Classically controlled Pauli: the gate's action on the
+                    # target when the control is |1>, applied when the
+                    # recorded result is 1.
+                    lookback = -min(pair)
+                    q = max(pair)
+                    if rec[len(rec) - lookback]:
+                        st.apply(PAULI[CONTROLLED_PAULI[name]], [q])
+                else:
+                    st.apply(UNITARIES[name], pair)
         elif name in ("M", "MR", "R"):
             for q in t:
                 p1 = st.prob_one(q)

@@ -7,15 +7,30 @@ TWO_Q = ["CX", "CY", "CZ", "SWAP"]
 COLLAPSE = ["R", "M", "MR"]
 
 
-def random_circuit(n, num_ops, seed, noise=False, p=0.01, collapse_weight=0.2):
+def random_circuit(n, num_ops, seed, noise=False, p=0.01, collapse_weight=0.2, feedback=0.0):
+    """feedback: probability per op of a classically controlled Pauli line
+    (CX / CY / CZ with a rec[-k] control, sometimes followed on the same line
+    by an ordinary pair of the same gate)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     lines = []
+    nm = 0
     for _ in range(num_ops):
+        if feedback and nm > 0 and rng.random() < feedback:
+            g = ["CX", "CY", "CZ"][int(rng.integers(3))]
+            rec = f"rec[-{int(rng.integers(1, min(nm, 6) + 1))}]"
+            q = str(int(rng.integers(n)))
+            pair = [q, rec] if g == "CZ" and rng.random() < 0.5 else [rec, q]
+            if n >= 2 and rng.random() < 0.3:
+                pair += list(map(str, rng.choice(n, size=2, replace=False)))
+            lines.append(g + " " + " ".join(pair))
+            continue
         r = rng.random()
         if r < collapse_weight:
             g = COLLAPSE[int(rng.integers(3))]
             k = int(rng.integers(1, min(3, n) + 1))
             qs = rng.choice(n, size=k, replace=False)
+            if g != "R":
+                nm += k
             lines.append(g + " " + " ".join(map(str, qs)))
         elif r < 0.6:
             g = ONE_Q[int(rng.integers(len(ONE_Q)))]
