@@ -160,6 +160,25 @@ def bench_formats(det, meas, rows_det, rows_meas, shots, reps: int = 3):
     return out
 
 
+def bench_feedback(steps: int, det, obs, stream):
+    """The same d=49 workload with ancillas reset by classically controlled X
+    (measurement + CX rec[-k] a) instead of R: detector-mode step time."""
+    import torch
+    from paper_2103_02202_amd import stim_gpu, workloads
+    circ = stim_gpu.Circuit(workloads.surface_code(D, ROUNDS, P, feedback_reset=True))
+    for _ in range(2):
+        stim_gpu.stim_detector_sample(circ.handle, SEED, 0, SHOTS, det, obs, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stim_gpu.stim_detector_sample(circ.handle, SEED, 0, SHOTS, det, obs, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": f"d={D}, {ROUNDS} rounds, p={P}, {SHOTS} shots, feedback resets",
+            "ms_per_step": dt * 1e3, "gate_targets": circ.num_gate_targets,
+            "shot_gates_per_s": circ.num_gate_targets * SHOTS / dt}
+
+
 def bench_serving(rates=(10, 30, 100, 300, 1000)):
     import torch
     from paper_2103_02202_amd import serve, workloads
@@ -202,6 +221,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-formats", action="store_true")
+    ap.add_argument("--no-feedback", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -311,6 +331,8 @@ def main():
     }
     if not args.no_formats:
         out["formats"] = bench_formats(det, meas, Dn, M, SHOTS)
+    if not args.no_feedback:
+        out["feedback"] = bench_feedback(max(3, args.steps // 2), det, obs, stream)
     if not args.no_batch:
         out["batch"] = bench_batch(max(3, args.steps // 2))
     if not args.no_serving:

@@ -65,8 +65,13 @@ typedef struct stim_circuit stim_circuit;   /* opaque, library-owned */
  * I X Y Z H H_XY H_YZ S S_DAG SQRT_X SQRT_X_DAG SQRT_Y SQRT_Y_DAG CX CY CZ SWAP
  * R M MR X_ERROR Y_ERROR Z_ERROR DEPOLARIZE1 DEPOLARIZE2 DETECTOR
  * OBSERVABLE_INCLUDE TICK QUBIT_COORDS SHIFT_COORDS REPEAT (and the aliases
- * CNOT ZCX ZCY ZCZ H_XZ SQRT_Z SQRT_Z_DAG RZ MZ MRZ).  Unknown gates give
- * STIM_E_UNSUPPORTED; syntax errors STIM_E_PARSE. */
+ * CNOT ZCX ZCY ZCZ H_XZ SQRT_Z SQRT_Z_DAG RZ MZ MRZ).  CX, CY and CZ also
+ * accept a measurement-record control rec[-k] in place of the control qubit
+ * (for CZ on either side): the Pauli X, Y or Z is applied to the other target
+ * when that result is 1 (Sec. 3, tracking corrections); such a pair counts as
+ * one gate target.  Unknown gates give STIM_E_UNSUPPORTED; syntax errors, a
+ * record as the target of CX / CY, records on both sides, or a lookback before
+ * the first measurement give STIM_E_PARSE. */
 int stim_compile(const char *text, size_t len, stim_circuit **out);
 
 /* Frees a handle and its device copies.  NULL is ignored.  The caller must

@@ -141,17 +141,27 @@ void parse_block(const std::vector<std::pair<const char *, const char *>> &lines
     } else if (!recs && !ann && !args.empty()) {
       fail(STIM_E_PARSE, c.line, "operation takes no arguments");
     }
+    const bool controllable = n.gate == G_CX || n.gate == G_CY || n.gate == G_CZ;
+    auto lookback = [&]() -> uint64_t {
+      std::string w = c.word();
+      if (w != "REC" || c.p + 2 > c.end || c.p[0] != '[' || c.p[1] != '-')
+        fail(STIM_E_PARSE, c.line, "expected rec[-k]");
+      c.p += 2;
+      uint64_t k = c.integer();
+      if (c.p >= c.end || *c.p != ']') fail(STIM_E_PARSE, c.line, "expected ']'");
+      c.p++;
+      if (k == 0) fail(STIM_E_PARSE, c.line, "bad lookback");
+      return k;
+    };
     while (!c.done()) {
       if (recs) {
-        std::string w = c.word();
-        if (w != "REC" || c.p + 2 > c.end || c.p[0] != '[' || c.p[1] != '-')
-          fail(STIM_E_PARSE, c.line, "expected rec[-k]");
-        c.p += 2;
-        uint64_t k = c.integer();
-        if (c.p >= c.end || *c.p != ']') fail(STIM_E_PARSE, c.line, "expected ']'");
-        c.p++;
-        if (k == 0 || k > 0xFFFFFFFFull) fail(STIM_E_PARSE, c.line, "bad lookback");
+        uint64_t k = lookback();
+        if (k > 0xFFFFFFFFull) fail(STIM_E_PARSE, c.line, "bad lookback");
         n.targets.push_back((uint32_t)k);
+      } else if (controllable && std::isalpha((unsigned char)*c.p)) {
+        uint64_t k = lookback();
+        if (k >= TGT_REC) fail(STIM_E_UNSUPPORTED, c.line, "lookback too large");
+        n.targets.push_back((uint32_t)k | TGT_REC);
       } else if (ann) {
         while (c.p < c.end && *c.p != ' ' && *c.p != '\t') c.p++;   // coordinates etc. ignored
       } else {
@@ -162,8 +172,13 @@ void parse_block(const std::vector<std::pair<const char *, const char *>> &lines
     }
     if (gate_is_two_qubit(n.gate)) {
       if (n.targets.size() % 2) fail(STIM_E_PARSE, c.line, "two-qubit operation needs pairs of targets");
-      for (size_t k = 0; k < n.targets.size(); k += 2)
-        if (n.targets[k] == n.targets[k + 1]) fail(STIM_E_PARSE, c.line, "two-qubit operation on one qubit");
+      for (size_t k = 0; k < n.targets.size(); k += 2) {
+        const bool ra = (n.targets[k] & TGT_REC) != 0, rb = (n.targets[k + 1] & TGT_REC) != 0;
+        if (ra && rb) fail(STIM_E_PARSE, c.line, "both targets are measurement records");
+        if (rb && n.gate != G_CZ) fail(STIM_E_PARSE, c.line, "a measurement record can only be the control");
+        if (!ra && !rb && n.targets[k] == n.targets[k + 1])
+          fail(STIM_E_PARSE, c.line, "two-qubit operation on one qubit");
+      }
     }
     out.push_back(std::move(n));
   }
@@ -213,7 +228,51 @@ struct Lowering {
     }
   }
 
+  // A CX / CY / CZ line with measurement-record controls: runs of ordinary
+  // pairs and runs of classically controlled pairs, in line order, each split
+  // where a qubit repeats.  Controlled pairs are stored as (qubit, lookback).
+  void emit_controlled_line(const Node &n) {
+    const OpCode quantum = opcode(n.gate);
+    const OpCode fb = n.gate == G_CX ? OP_FB_X : n.gate == G_CY ? OP_FB_Y : OP_FB_Z;
+    const size_t pairs = n.targets.size() / 2;
+    std::unordered_map<uint32_t, int> used;
+    bool first = true;
+    size_t s = 0;
+    while (s < pairs) {
+      auto is_fb = [&](size_t i) { return ((n.targets[2 * i] | n.targets[2 * i + 1]) & TGT_REC) != 0; };
+      const bool kind = is_fb(s);
+      used.clear();
+      DevOp op{};
+      op.code = (uint32_t)(kind ? fb : quantum) | (first ? OPF_NEW_INSTR : 0);
+      op.lead = first ? pending_lead : 0;
+      op.toff = (uint32_t)prog.targets.size();
+      op.slot0 = (uint32_t)s;
+      while (s < pairs && is_fb(s) == kind) {
+        uint32_t a = n.targets[2 * s], b = n.targets[2 * s + 1];
+        if (kind && (a & TGT_REC)) std::swap(a, b);          // (qubit, record)
+        if (used.count(a) || (!kind && used.count(b))) break;
+        used[a] = 1;
+        if (!kind) used[b] = 1;
+        prog.targets.push_back(a);
+        prog.targets.push_back(kind ? (b & ~TGT_REC) : b);
+        s++;
+        op.n++;
+      }
+      prog.ops.push_back(op);
+      first = false;
+    }
+    pending_lead = 0;
+  }
+
   void emit_line(const Node &n) {
+    if (n.gate == G_CX || n.gate == G_CY || n.gate == G_CZ) {
+      bool controlled = false;
+      for (uint32_t t : n.targets) controlled |= (t & TGT_REC) != 0;
+      if (controlled) {
+        emit_controlled_line(n);
+        return;
+      }
+    }
     OpCode code = opcode(n.gate);
     if (code == OP_COUNT || n.targets.empty() || (gate_is_noise(n.gate) && n.p == 0)) {
       pending_lead++;   // annotation, frame no-op or empty: only advances the flat index
@@ -340,7 +399,14 @@ struct Walker {
           if (gate_is_noise(n.gate)) {
             P.num_noise_targets += n.targets.size() / (gate_is_two_qubit(n.gate) ? 2 : 1);
           } else if (gate_is_clifford(n.gate)) {
-            for (uint32_t q : n.targets) touch(q, false, NONE);
+            for (uint32_t q : n.targets) {
+              if (q & TGT_REC) {
+                const uint64_t k = q & ~TGT_REC;
+                if (k > meas) fail(STIM_E_PARSE, n.line, "rec[-" + std::to_string(k) + "] reaches before the first measurement");
+                continue;
+              }
+              touch(q, false, NONE);
+            }
             P.num_gate_targets += n.targets.size() / (gate_is_two_qubit(n.gate) ? 2 : 1);
           }
           break;
@@ -355,7 +421,8 @@ uint64_t max_qubit(const std::vector<Node> &nodes) {
   for (const Node &n : nodes) {
     if (n.repeat) { m = std::max(m, max_qubit(n.body)); continue; }
     if (n.gate == G_DETECTOR || n.gate == G_OBSERVABLE_INCLUDE) continue;
-    for (uint32_t q : n.targets) m = std::max(m, (uint64_t)q + 1);
+    for (uint32_t q : n.targets)
+      if (!(q & TGT_REC)) m = std::max(m, (uint64_t)q + 1);
   }
   return m;
 }

@@ -32,9 +32,14 @@ struct Node {
   std::vector<Node> body;
   Gate gate = G_TICK;
   double p = 0;                    // noise probability / observable index
-  std::vector<uint32_t> targets;   // qubits, or lookbacks k of rec[-k]
+  std::vector<uint32_t> targets;   // qubits, or lookbacks k of rec[-k] (CX/CY/CZ: | TGT_REC)
   int line = 0;
 };
+
+// Flag on a CX / CY / CZ target in the parse tree: a measurement-record
+// control rec[-k] (k in the low bits) rather than a qubit (Sec. 3, tracking
+// corrections).
+constexpr uint32_t TGT_REC = 1u << 31;
 
 // Kernel operation codes.
 enum OpCode : uint32_t {
@@ -46,6 +51,10 @@ enum OpCode : uint32_t {
   OP_R, OP_M, OP_MR,
   OP_NOISE_X, OP_NOISE_Y, OP_NOISE_Z, OP_NOISE_DEP1, OP_NOISE_DEP2,
   OP_LOOP_BEGIN, OP_LOOP_END,
+  // Classically controlled Pauli X / Y / Z: pairs (qubit, lookback k); the
+  // frame of shots whose result k measurements back differs from the
+  // reference's takes the Pauli.
+  OP_FB_X, OP_FB_Y, OP_FB_Z,
   OP_COUNT
 };
 

@@ -341,6 +341,34 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
   } while (base < items);
 }
 
+// Classically controlled Pauli (Sec. 3, tracking corrections): for each pair
+// (qubit, lookback k) and word of the tile, the shots whose result k
+// measurements back differs from the reference's take the Pauli into their
+// frame.  That difference is read back from the record this workgroup wrote
+// (stored result XOR the reference bit): only this workgroup wrote those
+// words, so a workgroup-scope barrier (release and acquire over all memory)
+// and workgroup-scope loads make the stores of every wave visible.
+template <int T, bool IN_LDS>
+__device__ __forceinline__ void feedback_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
+                                            uint32_t code, uint64_t meas) {
+  __syncthreads();
+  const uint32_t items = op.n * T;
+  const uint32_t *tg = p.targets + op.toff;
+  for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+    const uint32_t k = it / T;
+    const int j = (int)(it % T);
+    if (j >= tl.valid) continue;
+    const uint32_t q = tg[2 * k];
+    const uint64_t m = meas - tg[2 * k + 1];
+    uint64_t f = __hip_atomic_load(p.out + m * p.out_stride + tl.tw0 + j, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (p.ref != nullptr && ((p.ref[m >> 6] >> (m & 63)) & 1)) f = ~f;
+    const auto ix = tl.at(q, j);
+    if (code != OP_FB_Z) tl.FX[ix] ^= f;
+    if (code != OP_FB_X) tl.FZ[ix] ^= f;
+  }
+}
+
 // Applies precomputed noise records: each names a qubit (and partner), a word
 // of the tile and up to five errors (6-bit position, 4-bit choice).
 template <int T, bool IN_LDS>
@@ -622,6 +650,8 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
         }
         noise_op<T, IN_LDS>(p, tl, op, code, instr, thr_lds);
       }
+    } else if (code >= OP_FB_X) {
+      feedback_op<T, IN_LDS>(p, tl, op, code, meas);
     } else {
       clifford_op<T, IN_LDS>(p, tl, op, code, stage_b);
     }

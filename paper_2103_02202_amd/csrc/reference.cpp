@@ -16,6 +16,7 @@
 // z bits packed in 64-bit words, plus a sign.  Column c < n is T(X_c); column
 // n + q is T(Z_q).
 #include <cstring>
+#include <utility>
 
 #include "circuit.h"
 
@@ -180,7 +181,19 @@ struct RefRun {
       }
       if (gate_is_clifford(n.gate)) {
         if (gate_is_two_qubit(n.gate)) {
-          for (size_t k = 0; k < n.targets.size(); k += 2) t.prepend(n.gate, n.targets[k], n.targets[k + 1]);
+          for (size_t k = 0; k < n.targets.size(); k += 2) {
+            uint32_t a = n.targets[k], b = n.targets[k + 1];
+            if ((a | b) & TGT_REC) {
+              // Classically controlled Pauli: applied when the reference's
+              // own result is 1.
+              if (a & TGT_REC) std::swap(a, b);
+              const uint64_t mi = m - (b & ~TGT_REC);
+              if ((bits[mi / 64] >> (mi % 64)) & 1)
+                t.prepend(n.gate == G_CX ? G_X : n.gate == G_CY ? G_Y : G_Z, a, a);
+              continue;
+            }
+            t.prepend(n.gate, a, b);
+          }
         } else {
           for (uint32_t q : n.targets) t.prepend(n.gate, q, q);
         }

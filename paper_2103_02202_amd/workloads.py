@@ -65,7 +65,10 @@ def _surface_layout(d: int):
     return data, anc, index
 
 
-def surface_code(d: int, rounds: int, p: float) -> str:
+def surface_code(d: int, rounds: int, p: float, feedback_reset: bool = False) -> str:
+    """Rotated surface-code memory experiment.  feedback_reset: ancillas are
+    reset after their measurement by a classically controlled X (CX rec[-k] a)
+    instead of an R at the start of the next round (adaptive circuit)."""
     if d < 3 or d % 2 == 0:
         raise ValueError("d must be odd and >= 3")
     data, anc, idx = _surface_layout(d)
@@ -96,11 +99,14 @@ def surface_code(d: int, rounds: int, p: float) -> str:
         return [f"{name}({p!r}) {j(targets)}"] if p > 0 and targets else []
 
     def round_body(first: bool):
-        out = [f"R {j(qa)}", "TICK", f"H {j(qx)}"] + noise("DEPOLARIZE1", qx) + ["TICK"]
+        out = [f"R {j(qa)}", "TICK"] if first or not feedback_reset else []
+        out += [f"H {j(qx)}"] + noise("DEPOLARIZE1", qx) + ["TICK"]
         for pairs in layers:
             out += [f"CX {j(pairs)}"] + noise("DEPOLARIZE2", pairs) + ["TICK"]
         out += [f"H {j(qx)}"] + noise("DEPOLARIZE1", qx) + ["TICK"]
         out += noise("X_ERROR", qa) + [f"M {j(qa)}"]
+        if feedback_reset:
+            out.append("CX " + " ".join(f"rec[-{A - k}] {a}" for k, a in enumerate(qa)))
         for k, (x, y, is_x) in enumerate(anc):
             back = A - k
             if first:

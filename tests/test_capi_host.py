@@ -67,6 +67,26 @@ def test_reference_matches_oracle_on_random_circuits(seed):
     assert np.array_equal(unpack_ref(c.reference(), c.num_measurements), o.reference())
 
 
+@pytest.mark.parametrize("seed", range(20))
+def test_reference_with_feedback_matches_oracle(seed):
+    rng = np.random.Generator(np.random.PCG64(300 + seed))
+    n = int(rng.integers(2, 30))
+    text = random_circuit(n, int(rng.integers(20, 300)), seed=9500 + seed, noise=True, feedback=0.15)
+    c, o = sg.Circuit(text), oracle.Circuit(text)
+    assert (c.num_qubits, c.num_measurements, c.num_gate_targets) == \
+        (o.num_qubits, o.num_measurements, o.num_gate_targets)
+    assert np.array_equal(unpack_ref(c.reference(), c.num_measurements), o.reference())
+
+
+def test_reference_with_feedback_inside_repeat_blocks():
+    # The lookback is relative to each iteration's own measurements.
+    text = "X 0\nREPEAT 5 {\n  M 0\n  CX rec[-1] 1\n  M 1\n  CX rec[-1] 1\n  X 0\n}\n"
+    c, o = sg.Circuit(text), oracle.Circuit(text)
+    want = o.reference()
+    assert want.tolist() == [1, 1, 0, 0, 1, 1, 0, 0, 1, 1]
+    assert np.array_equal(unpack_ref(c.reference(), c.num_measurements), want)
+
+
 def test_surface_closed_form_counts():
     for d in (3, 5, 9):
         c = sg.Circuit(wl.surface_code(d, d, 1e-3))
@@ -88,6 +108,14 @@ def test_surface_closed_form_counts():
     ("M 0\nDETECTOR rec[-2]", sg.STIM_E_PARSE),
     ("H(0.5) 0", sg.STIM_E_PARSE),
     ("AMPLITUDE_DAMP(0.1) 0", sg.STIM_E_UNSUPPORTED),
+    ("M 0\nCX 1 rec[-1]", sg.STIM_E_PARSE),
+    ("M 0\nCY 1 rec[-1]", sg.STIM_E_PARSE),
+    ("M 0 1\nCZ rec[-1] rec[-2]", sg.STIM_E_PARSE),
+    ("CX rec[-1] 0", sg.STIM_E_PARSE),
+    ("M 0\nCX rec[-2] 1", sg.STIM_E_PARSE),
+    ("M 0\nCX rec[-0] 1", sg.STIM_E_PARSE),
+    ("M 0\nH rec[-1]", sg.STIM_E_PARSE),
+    ("M 0\nSWAP rec[-1] 1", sg.STIM_E_PARSE),
 ])
 def test_compile_errors(text, code):
     with pytest.raises(sg.StimError) as e:

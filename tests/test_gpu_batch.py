@@ -130,3 +130,25 @@ def test_batch_rejects_bad_requests(sg):
     with pytest.raises(sg.StimError):
         sg.stim_batch_sample([{"handle": c.handle, "seed": 0, "shot_offset": 0, "num_shots": 64, "mode": 7,
                                "out0": out, "out1": None}])
+
+
+def test_batch_with_feedback_requests(sg):
+    """Classically controlled Paulis inside the persistent batched kernel."""
+    announce("batch with feedback")
+    specs = [
+        (wl.surface_code(5, 5, 1e-2, feedback_reset=True), 3000, 11, 1, 0),
+        (random_circuit(12, 120, seed=91, noise=True, p=0.05, feedback=0.2), 2222, 12, 0, 64),
+        (wl.surface_code(3, 3, 1e-3), 1024, 13, 1, 0),
+        (wl.surface_code(7, 7, 3e-3, feedback_reset=True), 4500, 14, 0, 0),
+    ]
+    reqs, circs = make_requests(sg, specs)
+    for _ in range(3):                       # direct, tuned + captured, replay
+        for r in reqs:
+            r["out0"].fill_(-1)
+        sg.stim_batch_sample(reqs)
+        torch.cuda.synchronize()
+        check_against_single(sg, reqs, circs)
+    for (text, shots, seed, mode, offset), r in zip(specs, reqs):
+        o = oracle.Circuit(text)
+        want = o.sample(seed, offset, shots, meas=mode == 0, det=mode == 1, obs=mode == 1)
+        assert np.array_equal(r["out0"].cpu().numpy().view(np.uint64), want["meas" if mode == 0 else "det"])

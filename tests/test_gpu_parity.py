@@ -226,3 +226,58 @@ def test_global_frame_workgroups_take_tiles_in_turn(sg, tile, slots, threads, mo
     monkeypatch.setenv("STIM_FRAME_THREADS", threads)
     check_meas(sg, text, 21, shots)
     check_det(sg, text, 21, shots)
+
+
+# --- classically controlled Paulis (Sec. 3, tracking corrections) ----------
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_feedback_circuits(sg, seed):
+    rng = np.random.Generator(np.random.PCG64(500 + seed))
+    n = int(rng.integers(2, 50))
+    text = random_circuit(n, int(rng.integers(20, 250)), seed=8000 + seed, noise=True,
+                          p=float(rng.choice([1e-3, 0.05, 0.5])), feedback=0.15)
+    shots = int(rng.integers(1, 5000))
+    announce("random feedback", seed, n, shots)
+    check_meas(sg, text, seed, shots)
+
+
+def test_feedback_teleportation_and_deterministic_cases(sg):
+    announce("feedback teleportation")
+    for prep, undo in [("H 0\nS 0", "S_DAG 2\nH 2"), ("X 0\nH 0", "H 2\nX 2")]:
+        text = f"{prep}\nH 1\nCX 1 2\nCX 0 1\nH 0\nM 0 1\nCX rec[-1] 2\nCZ 2 rec[-2]\n{undo}\nM 2\n"
+        check_meas(sg, text, 1, 3000)
+        c = sg.Circuit(text)
+        assert int(torch.count_nonzero(c.sample(1, 3000)[2])) == 0
+    for text in ["X 0\nM 0\nH 1\nCY rec[-1] 1\nH 1\nM 1\n", "X_ERROR(1) 0\nM 0\nH 1\nCY rec[-1] 1\nH 1\nM 1\n",
+                 "X 0\nM 0 1\nCX rec[-2] 2 rec[-1] 3 2 3\nM 2 3\n"]:
+        check_meas(sg, text, 2, 700)
+
+
+@pytest.mark.parametrize("tile,placement", [("1", "lds"), ("4", "lds"), ("2", "global"), ("16", "global")])
+def test_feedback_reset_surface_code_tilings(sg, tile, placement, monkeypatch):
+    announce("feedback surface d5", tile, placement)
+    monkeypatch.setenv("STIM_TILE_WORDS", tile)
+    monkeypatch.setenv("STIM_FRAME_PLACEMENT", placement)
+    text = wl.surface_code(5, 5, 0.01, feedback_reset=True)
+    check_meas(sg, text, 4, 5000)
+    check_det(sg, text, 4, 5000)
+
+
+def test_feedback_reset_surface_d15(sg):
+    """d=15 with feedback resets: noiseless detectors are all zero at 2^16
+    shots; noisy slices of a 2^18-shot run match the oracle."""
+    announce("feedback surface d15")
+    c0 = sg.Circuit(wl.surface_code(15, 15, 0.0, feedback_reset=True))
+    det, obs = c0.detect(0, 1 << 16)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(det)) == 0 and int(torch.count_nonzero(obs)) == 0
+    text = wl.surface_code(15, 15, 1e-3, feedback_reset=True)
+    c, o = sg.Circuit(text), oracle.Circuit(text)
+    full = c.sample(3, 1 << 18)
+    det, obs = c.detect(3, 1 << 18)
+    torch.cuda.synchronize()
+    for w0 in (0, 1234, 4095):
+        want = o.sample(3, 64 * w0, 64, meas=True, det=True, obs=True)
+        assert np.array_equal(full[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["meas"])
+        assert np.array_equal(det[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["det"])
+        assert np.array_equal(obs[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["obs"])
