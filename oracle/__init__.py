@@ -62,6 +62,9 @@ def lib():
         L.oracle_gate.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
         L.oracle_conjugate.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]
         L.oracle_z_image.argtypes = [p, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_size_t]
+        L.oracle_error_sets.argtypes = [p, p, p, p, p]
+        L.oracle_deterministic.argtypes = [p]
+        L.oracle_sparse_detect.argtypes = [p, u64, u64, u64, p, p, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -137,6 +140,36 @@ class Circuit:
             buf = np.zeros(n, dtype=np.uint64)
             lib().oracle_detector(self._h, d, _ptr(buf), n)
         return [int(v) for v in buf[:n]]
+
+    def error_sets(self):
+        """Detectors / observables flipped by each single-Pauli error (Sec. 5.6):
+        (off, lanes) with generator g's lanes in lanes[off[g]:off[g + 1]];
+        generators by noise instruction (p > 0), slot, then X, Z of each qubit.
+        Lane d < num_detectors is detector d, lane num_detectors + o is
+        observable o."""
+        n_sets, n_ent = ctypes.c_uint64(), ctypes.c_uint64()
+        L = lib()
+        if L.oracle_error_sets(self._h, ctypes.byref(n_sets), ctypes.byref(n_ent), None, None) != 0:
+            raise OracleError(L.oracle_last_error().decode())
+        off = np.zeros(n_sets.value + 1, dtype=np.uint64)
+        lanes = np.zeros(max(n_ent.value, 1), dtype=np.uint32)
+        L.oracle_error_sets(self._h, ctypes.byref(n_sets), ctypes.byref(n_ent), _ptr(off), _ptr(lanes))
+        return off, lanes[: n_ent.value]
+
+    def deterministic(self) -> bool:
+        return lib().oracle_deterministic(self._h) == 1
+
+    def sparse_detect(self, seed: int, shot_offset: int, num_shots: int, threads: int | None = None):
+        """Sparse detection-event sampling (Sec. 5.6): (det [D][W], obs [L][W])."""
+        W = (num_shots + 63) // 64
+        det = np.zeros((self.num_detectors, W), dtype=np.uint64)
+        obs = np.zeros((self.num_observables, W), dtype=np.uint64)
+        rc = lib().oracle_sparse_detect(self._h, seed, shot_offset, num_shots,
+                                        _ptr(det) if det.size else None, _ptr(obs) if obs.size else None,
+                                        threads or os.cpu_count() or 1)
+        if rc != 0:
+            raise OracleError(lib().oracle_last_error().decode())
+        return det, obs
 
     def z_image(self, q: int) -> str:
         out = ctypes.create_string_buffer(self.num_qubits + 8)

@@ -817,8 +817,137 @@ void simulate_word(const Circuit &c, const std::vector<uint8_t> &ref, const std:
   (void)ref;
 }
 
+// ---------------------------------------------------------------------------
+// Sparse detection-event sampling (Sec. 5.6): sample the error events, then
+// XOR together the sets of detectors (and observables) each one flips.  A
+// set is found by its plain definition: insert the single Pauli into an
+// otherwise noiseless frame whose Z randomisations are all zero, run the rest
+// of the circuit and see which detectors change.  Errors come from the same
+// draws as in the frame simulation, so on circuits whose detectors and
+// observables are deterministic both methods give the same events.
+// Lanes number the outputs: detector d is lane d, observable o is lane
+// num_det + o.
+// ---------------------------------------------------------------------------
+struct ErrorSets {
+  // Generators in order: noise instruction (p > 0, circuit order), slot, then
+  // X and Z of the slot's first qubit and (two-qubit channels) of its second.
+  std::vector<uint64_t> off{0};   // generator g: lanes[off[g], off[g + 1])
+  std::vector<uint32_t> lanes;
+  std::vector<uint64_t> first;    // per instruction: its first generator
+};
+
+// Lanes flipped by X (xz = 0) or Z (xz = 1) on qubit q right after
+// instruction `at`.
+void inject(const Circuit &c, const std::vector<FrameRule> &rules, size_t at, uint64_t meas_done, uint32_t q,
+            int xz, std::vector<uint32_t> &out) {
+  std::vector<uint8_t> x(c.num_qubits, 0), z(c.num_qubits, 0), flips(c.num_meas, 0);
+  (xz ? z : x)[q] = 1;
+  uint64_t m = meas_done;
+  for (size_t i = at + 1; i < c.ops.size(); i++) {
+    const Instr &ins = c.ops[i];
+    const GateInfo &g = GATES[ins.gate];
+    if (g.kind == K_CLIFFORD1 || g.kind == K_CLIFFORD2) {
+      const FrameRule &r = rules[ins.gate];
+      for (size_t s = 0; s < ins.q.size(); s += r.k) {
+        uint32_t fq;
+        uint64_t fm;
+        int pauli;
+        if (r.k == 2 && controlled_pair(ins, s, fq, fm, pauli)) {
+          if (pauli & 1) x[fq] ^= flips[fm];
+          if (pauli & 2) z[fq] ^= flips[fm];
+          continue;
+        }
+        uint8_t in[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+        for (int t = 0; t < r.k; t++) { in[2 * t] = x[ins.q[s + t]]; in[2 * t + 1] = z[ins.q[s + t]]; }
+        for (int gen = 0; gen < 2 * r.k; gen++)
+          for (int k = 0; k < 2 * r.k; k++)
+            if (r.img[gen][k]) o[k] ^= in[gen];
+        for (int t = 0; t < r.k; t++) { x[ins.q[s + t]] = o[2 * t]; z[ins.q[s + t]] = o[2 * t + 1]; }
+      }
+    } else if (g.kind == K_RESET || g.kind == K_MEASURE || g.kind == K_MEASURE_RESET) {
+      for (uint32_t t : ins.q) {
+        if (g.kind != K_RESET) flips[m++] = x[t];
+        if (g.kind != K_MEASURE) { x[t] = 0; z[t] = 0; }
+      }
+    }
+  }
+  out.clear();
+  for (uint64_t d = 0; d < c.num_det; d++) {
+    uint8_t v = 0;
+    for (uint64_t mi : c.detectors[d]) v ^= flips[mi];
+    if (v) out.push_back((uint32_t)d);
+  }
+  for (uint64_t o = 0; o < c.num_obs; o++) {
+    uint8_t v = 0;
+    for (uint64_t mi : c.observables[o]) v ^= flips[mi];
+    if (v) out.push_back((uint32_t)(c.num_det + o));
+  }
+}
+
+std::vector<FrameRule> all_frame_rules() {
+  std::vector<FrameRule> rules(NUM_GATES);
+  for (int g = 0; g < NUM_GATES; g++)
+    if (GATES[g].kind == K_CLIFFORD1 || GATES[g].kind == K_CLIFFORD2) rules[g] = frame_rule(g);
+  return rules;
+}
+
+ErrorSets error_sets(const Circuit &c) {
+  ErrorSets e;
+  std::vector<FrameRule> rules = all_frame_rules();
+  std::vector<uint32_t> lanes;
+  uint64_t meas = 0;
+  e.first.assign(c.ops.size(), ~0ull);
+  for (size_t i = 0; i < c.ops.size(); i++) {
+    const Instr &ins = c.ops[i];
+    const GateInfo &g = GATES[ins.gate];
+    if ((g.kind == K_NOISE1 || g.kind == K_NOISE2) && ins.p > 0) {
+      e.first[i] = e.off.size() - 1;
+      for (uint32_t q : ins.q)
+        for (int xz = 0; xz < 2; xz++) {
+          inject(c, rules, i, meas, q, xz, lanes);
+          e.lanes.insert(e.lanes.end(), lanes.begin(), lanes.end());
+          e.off.push_back(e.lanes.size());
+        }
+    }
+    if (g.kind == K_MEASURE || g.kind == K_MEASURE_RESET) meas += ins.q.size();
+  }
+  return e;
+}
+
+// True when no detector or observable depends on the random outcomes of the
+// noiseless circuit: with noise switched off, a frame run with random Z
+// randomisations must leave every detector and observable at zero (a
+// dependence escapes with probability 2^-64 per word; two words are run).
+bool deterministic(const Circuit &c) {
+  Circuit quiet = c;
+  for (Instr &ins : quiet.ops) ins.p = 0;
+  std::vector<FrameRule> rules = all_frame_rules();
+  std::vector<std::vector<uint64_t>> thr(quiet.ops.size());
+  std::vector<uint8_t> ref;
+  std::vector<uint64_t> flips;
+  for (uint64_t word = 0; word < 2; word++) {
+    simulate_word(quiet, ref, rules, thr, 0x5eed + word, word, ~0ull, flips);
+    for (const auto &d : c.detectors) {
+      uint64_t v = 0;
+      for (uint64_t mi : d) v ^= flips[mi];
+      if (v) return false;
+    }
+    for (const auto &o : c.observables) {
+      uint64_t v = 0;
+      for (uint64_t mi : o) v ^= flips[mi];
+      if (v) return false;
+    }
+  }
+  return true;
+}
+
 struct Handle {
   Circuit c;
+  std::unique_ptr<ErrorSets> sets;
+  const ErrorSets &error_sets_cached() {
+    if (!sets) sets = std::make_unique<ErrorSets>(error_sets(c));
+    return *sets;
+  }
 };
 
 }  // namespace
@@ -930,6 +1059,87 @@ int oracle_sample(void *hv, const uint8_t *ref, uint64_t seed, uint64_t shot_off
         }
         obs[o * W + w] = acc ^ expect;
       }
+  }
+  return 0;
+}
+
+// Error sets: *num_sets generators (see ErrorSets) and *num_entries lanes;
+// off (num_sets + 1 entries) and lanes are filled when not null.
+int oracle_error_sets(void *hv, uint64_t *num_sets, uint64_t *num_entries, uint64_t *off, uint32_t *lanes) {
+  try {
+    const ErrorSets &e = ((Handle *)hv)->error_sets_cached();
+    *num_sets = e.off.size() - 1;
+    *num_entries = e.lanes.size();
+    if (off) std::memcpy(off, e.off.data(), e.off.size() * sizeof(uint64_t));
+    if (lanes && !e.lanes.empty()) std::memcpy(lanes, e.lanes.data(), e.lanes.size() * sizeof(uint32_t));
+    return 0;
+  } catch (const std::exception &ex) {
+    g_err = ex.what();
+    return -1;
+  }
+}
+
+// 1 when every detector and observable is deterministic, else 0.
+int oracle_deterministic(void *hv) { return deterministic(((Handle *)hv)->c) ? 1 : 0; }
+
+// Sparse detection-event sampling of shots [shot_offset, shot_offset +
+// num_shots): det [D][W], obs [L][W] as in oracle_sample (either may be null).
+// Fails (-3) when a detector or observable is not deterministic.
+int oracle_sparse_detect(void *hv, uint64_t seed, uint64_t shot_offset, uint64_t num_shots, uint64_t *det,
+                         uint64_t *obs, int threads) {
+  Handle *h = (Handle *)hv;
+  const Circuit &c = h->c;
+  if (shot_offset % 64 != 0 || num_shots == 0) { g_err = "bad shot range"; return -2; }
+  if (!deterministic(c)) { g_err = "a detector or observable is not deterministic"; return -3; }
+  const ErrorSets &e = h->error_sets_cached();
+  const uint64_t W = (num_shots + 63) / 64;
+  if (det) std::memset(det, 0, c.num_det * W * sizeof(uint64_t));
+  if (obs) std::memset(obs, 0, c.num_obs * W * sizeof(uint64_t));
+  std::vector<std::vector<uint64_t>> thr(c.ops.size());
+  for (size_t i = 0; i < c.ops.size(); i++)
+    if (e.first[i] != ~0ull) {
+      thr[i].resize(64);
+      thresholds(c.ops[i].p, thr[i].data());
+    }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads > 0 ? threads : 1)
+  for (uint64_t w = 0; w < W; w++) {
+    const uint64_t word = shot_offset / 64 + w;
+    std::vector<std::pair<int, int>> hits;
+    for (size_t i = 0; i < c.ops.size(); i++) {
+      if (e.first[i] == ~0ull) continue;
+      const Instr &ins = c.ops[i];
+      const NoiseType nt = GATES[ins.gate].noise;
+      const int k = nt == N_DEP2 ? 2 : 1;
+      for (size_t s = 0; s < ins.q.size() / k; s++) {
+        sample_hits(seed, i, s, word, thr[i].data(), nt == N_DEP1 ? 3 : nt == N_DEP2 ? 15 : 0, hits);
+        for (auto &hit : hits) {
+          if (64 * w + (uint64_t)hit.first >= num_shots) continue;   // past the last shot
+          // Generator bits: X_a, Z_a, X_b, Z_b.
+          int gens = 0;
+          switch (nt) {
+            case N_X: gens = 1; break;
+            case N_Y: gens = 3; break;
+            case N_Z: gens = 2; break;
+            case N_DEP1: gens = hit.second == 0 ? 1 : hit.second == 1 ? 3 : 2; break;
+            case N_DEP2: gens = hit.second + 1; break;
+            default: break;
+          }
+          const uint64_t bit = 1ull << hit.first;
+          for (int gbit = 0; gbit < 2 * k; gbit++) {
+            if (!((gens >> gbit) & 1)) continue;
+            const uint64_t gid = e.first[i] + s * 2 * k + gbit;
+            for (uint64_t a = e.off[gid]; a < e.off[gid + 1]; a++) {
+              const uint64_t lane = e.lanes[a];
+              if (lane < c.num_det) {
+                if (det) det[lane * W + w] ^= bit;
+              } else if (obs) {
+                obs[(lane - c.num_det) * W + w] ^= bit;
+              }
+            }
+          }
+        }
+      }
+    }
   }
   return 0;
 }
