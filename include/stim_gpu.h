@@ -106,6 +106,31 @@ int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint
 int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
                          uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
 
+/* Sparse detection-event sampling (Sec. 5.6: draw the errors, XOR the sets
+ * of detectors each one flips).  Same arguments, output layout and results as
+ * stim_detector_sample: the errors are drawn from the frame sampler's own
+ * random streams, so the events are bit-identical, while the work is one
+ * generator call per 32 noise sites and 64 shots plus the errors themselves
+ * instead of a pass over every gate.  The error sets are built on the host on
+ * the first call (cached in the handle).  Returns STIM_E_UNSUPPORTED (message
+ * in stim_last_error) when a detector or observable depends on a random
+ * measurement outcome, for classically controlled Paulis, and for circuits
+ * whose noise executions cannot be tabulated. */
+int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
+                                uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
+
+/* The error sets behind stim_sparse_detector_sample (host only, no GPU
+ * needed).  Generators are numbered by noise execution in circuit order
+ * (noise instructions with p > 0, unrolled), then slot, then X and Z of the
+ * slot's first qubit and (two-qubit channels) of its second.  Generator g
+ * flips lanes[offsets[g] .. offsets[g + 1]) in increasing order, lane d <
+ * num_detectors being detector d and lane num_detectors + o observable o.
+ * *num_sets and *num_entries (host) receive the sizes; offsets (num_sets + 1
+ * uint32) and lanes (num_entries uint32) are host buffers filled when not
+ * NULL.  Errors as stim_sparse_detector_sample. */
+int stim_error_sets(stim_circuit *c, uint64_t *num_sets, uint64_t *num_entries, uint32_t *offsets,
+                    uint32_t *lanes);
+
 /* One request of a batched launch. mode 0: out0 = measurement record
  * (as stim_frame_sample); mode 1: out0 = detection events, out1 = observable
  * flips or NULL (as stim_detector_sample). */

@@ -16,8 +16,8 @@ LIB = os.path.join(HERE, "libstimgpu.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SOURCES = ["circuit.cpp", "reference.cpp"]
-HIP_SOURCES = ["frame_kernels.hip", "format_kernels.hip", "capi.hip"]
+HOST_SOURCES = ["circuit.cpp", "reference.cpp", "error_sets.cpp"]
+HIP_SOURCES = ["frame_kernels.hip", "format_kernels.hip", "sparse_kernels.hip", "capi.hip"]
 
 # Packed-FP32 instructions are kept out of every HIP object.
 # Private arrays must not be promoted into LDS: the frame slice uses it all.
@@ -25,7 +25,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-disable-promote-alloca-to-lds"]
-HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-march=x86-64-v3", "-I", INCLUDE]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-march=x86-64-v3", "-pthread", "-I", INCLUDE]
 
 
 def _run(cmd):
@@ -52,7 +52,7 @@ def build(verbose: bool = False) -> str:
             if verbose and res.stderr.strip():
                 print(res.stderr, file=sys.stderr)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

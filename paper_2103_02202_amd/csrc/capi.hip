@@ -16,6 +16,7 @@
 #include "circuit.h"
 #include "format_kernels.h"
 #include "frame_kernels.h"
+#include "sparse_kernels.h"
 
 using namespace stimgpu;
 
@@ -41,6 +42,9 @@ struct DeviceCopy {
   uint32_t *det_off = nullptr, *det_idx = nullptr, *obs_off = nullptr, *obs_idx = nullptr, *det_order = nullptr;
   uint32_t *noise_pc = nullptr;
   uint64_t *noise_instr = nullptr;
+  // Error sets of sparse detection sampling (uploaded on its first use).
+  uint64_t *gen_base = nullptr;
+  uint32_t *set_off = nullptr, *set_lanes = nullptr;
 };
 
 }  // namespace
@@ -52,6 +56,13 @@ struct stim_circuit {
   bool have_ref = false;
   std::vector<uint64_t> ref;
   std::map<int, DeviceCopy> dev;
+  // Error sets (sparse detection sampling): built on first use; a circuit
+  // they cannot serve keeps its error.
+  bool have_em = false;
+  int em_code = 0;
+  std::string em_msg;
+  ErrorModel em;
+  uint32_t em_max_groups = 0;     // most 32-slot groups of one noise execution
 };
 
 namespace {
@@ -123,6 +134,39 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   c->dev[dev] = d;
   *out = &c->dev[dev];
+  return STIM_OK;
+}
+
+int ensure_error_model(stim_circuit *c) {
+  if (!c->have_em) {
+    c->have_em = true;
+    try {
+      c->em = build_error_model(c->prog);
+      for (uint32_t pc : c->prog.noise_pc) {
+        const DevOp &op = c->prog.ops[pc];
+        if (op.n >= (1u << 24)) throw CompileError{STIM_E_UNSUPPORTED, "noise instruction with 2^24 or more sites"};
+        const uint32_t groups = ((op.slot0 + op.n - 1) >> 5) - (op.slot0 >> 5) + 1;
+        c->em_max_groups = std::max(c->em_max_groups, groups);
+      }
+    } catch (const CompileError &e) {
+      c->em_code = e.code;
+      c->em_msg = e.msg;
+    } catch (const std::bad_alloc &) {
+      c->em_code = STIM_E_OOM;
+      c->em_msg = "out of host memory building the error sets";
+    }
+  }
+  return c->em_code ? set_error(c->em_code, c->em_msg) : STIM_OK;
+}
+
+int ensure_sparse_device(stim_circuit *c, DeviceCopy *d, hipStream_t s) {
+  if (d->set_off) return STIM_OK;
+  hipError_t e;
+  if ((e = upload(c->em.gen_base, &d->gen_base, s)) != hipSuccess ||
+      (e = upload(c->em.set_off, &d->set_off, s)) != hipSuccess ||
+      (e = upload(c->em.set_lanes, &d->set_lanes, s)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? set_error(STIM_E_OOM, "device allocation failed") : hip_error(e, "upload");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   return STIM_OK;
 }
 
@@ -782,8 +826,9 @@ void stim_circuit_free(stim_circuit *c) {
   for (auto &kv : c->dev) {
     (void)hipSetDevice(kv.first);
     DeviceCopy &d = kv.second;
-    void *ptrs[] = {d.ops,     d.targets, d.thresholds, d.ref,      d.det_off,   d.det_idx,
-                    d.obs_off, d.obs_idx, d.det_order,  d.noise_pc, d.noise_instr};
+    void *ptrs[] = {d.ops,       d.targets,     d.thresholds, d.ref,     d.det_off,
+                    d.det_idx,   d.obs_off,     d.obs_idx,    d.det_order, d.noise_pc,
+                    d.noise_instr, d.gen_base, d.set_off,    d.set_lanes};
     for (void *p : ptrs) if (p) (void)hipFree(p);
   }
   if (!c->dev.empty()) (void)hipSetDevice(cur);
@@ -857,6 +902,67 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   hipError_t fe = hipFreeAsync(flips, s);
   if (!rc && fe != hipSuccess) rc = hip_error(fe, "hipFreeAsync");
   return rc;
+}
+
+int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
+                                uint64_t *out_det, uint64_t *out_obs, void *hip_stream) {
+  int rc = check_sample_args(c, shot_offset, num_shots);
+  if (rc) return rc;
+  if (c->prog.num_detectors > 0 && !is_device_pointer(out_det))
+    return set_error(STIM_E_INVALID_ARG, "out_det is not a device pointer");
+  if (out_obs && c->prog.num_observables > 0 && !is_device_pointer(out_obs))
+    return set_error(STIM_E_INVALID_ARG, "out_obs is not a device pointer");
+  const uint64_t W = (num_shots + 63) / 64;
+  if (W >= (1ull << 32)) return set_error(STIM_E_UNSUPPORTED, "too many shots in one call");
+  hipStream_t s = (hipStream_t)hip_stream;
+  DeviceCopy *d = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    if ((rc = ensure_error_model(c))) return rc;
+    if ((rc = ensure_reference(c))) return rc;
+    if ((rc = ensure_device(c, s, &d))) return rc;
+    if ((rc = ensure_sparse_device(c, d, s))) return rc;
+  }
+  const Program &P = c->prog;
+  hipError_t e;
+  if (P.num_detectors && (e = hipMemsetAsync(out_det, 0, P.num_detectors * W * sizeof(uint64_t), s)) != hipSuccess)
+    return hip_error(e, "hipMemsetAsync");
+  if (out_obs && P.num_observables &&
+      (e = hipMemsetAsync(out_obs, 0, P.num_observables * W * sizeof(uint64_t), s)) != hipSuccess)
+    return hip_error(e, "hipMemsetAsync");
+  SparseParams sp{};
+  sp.ops = d->ops;
+  sp.targets = d->targets;
+  sp.thresholds = d->thresholds;
+  sp.inst_pc = d->noise_pc;
+  sp.inst_instr = d->noise_instr;
+  sp.gen_base = d->gen_base;
+  sp.set_off = d->set_off;
+  sp.set_lanes = d->set_lanes;
+  sp.seed = seed;
+  sp.word0 = shot_offset / 64;
+  sp.num_words = W;
+  sp.num_shots = num_shots;
+  sp.det = out_det;
+  sp.obs = P.num_observables ? out_obs : nullptr;
+  sp.num_det = (uint32_t)P.num_detectors;
+  if ((e = launch_sparse_events(sp, (uint32_t)P.noise_pc.size(), (uint64_t)c->em_max_groups * W, s)) != hipSuccess)
+    return hip_error(e, "sparse event kernel launch");
+  return STIM_OK;
+}
+
+int stim_error_sets(stim_circuit *c, uint64_t *num_sets, uint64_t *num_entries, uint32_t *offsets,
+                    uint32_t *lanes) {
+  if (!c || !num_sets || !num_entries) return set_error(STIM_E_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lock(c->mu);
+  int rc = ensure_error_model(c);
+  if (rc) return rc;
+  *num_sets = c->em.num_generators;
+  *num_entries = c->em.set_lanes.size();
+  if (offsets) std::memcpy(offsets, c->em.set_off.data(), c->em.set_off.size() * sizeof(uint32_t));
+  if (lanes && !c->em.set_lanes.empty())
+    std::memcpy(lanes, c->em.set_lanes.data(), c->em.set_lanes.size() * sizeof(uint32_t));
+  return STIM_OK;
 }
 
 int stim_format_shots(const uint64_t *table, uint64_t rows, uint64_t num_shots, int format, uint8_t *out,

@@ -111,6 +111,21 @@ Program compile_program(const std::vector<Node> &tree);
 // Canonical reference sample (Sec. 4); bit m of the result = measurement m.
 std::vector<uint64_t> reference_sample(const std::vector<Node> &tree, uint64_t num_qubits,
                                        uint64_t num_measurements);
+// Detectors and observables flipped by each single-Pauli error (Sec. 5.6),
+// for sparse detection-event sampling.  Generators are numbered by noise
+// execution (walk order), slot, then X and Z of the slot's first qubit and of
+// its second (two-qubit channels); lane d < D is detector d, lane D + o is
+// observable o.
+struct ErrorModel {
+  uint64_t num_generators = 0;
+  std::vector<uint64_t> gen_base;     // per noise execution: its first generator
+  std::vector<uint32_t> set_off;      // generator g: set_lanes[set_off[g] .. set_off[g + 1])
+  std::vector<uint32_t> set_lanes;
+};
+// Builds the error sets by a backward sensitivity walk (throws CompileError
+// with STIM_E_UNSUPPORTED for random detectors or observables, classically
+// controlled Paulis, or circuits too long to tabulate).
+ErrorModel build_error_model(const Program &P);
 // Gap-sampling thresholds t[0..63] of probability p (exact integer recurrence).
 void noise_thresholds(double p, uint64_t *t);
 

@@ -46,6 +46,8 @@ def lib():
         L.stim_reference_sample.argtypes = [vp, vp]
         L.stim_frame_sample.argtypes = [vp, u64, u64, u64, vp, vp]
         L.stim_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
+        L.stim_sparse_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
+        L.stim_error_sets.argtypes = [vp, P64, P64, vp, vp]
         L.stim_batch_sample.argtypes = [ctypes.POINTER(StimRequest), ctypes.c_size_t, vp]
         L.stim_format_shots.argtypes = [vp, u64, u64, ctypes.c_int, vp, u64, P64, vp]
         L.stim_kernel_timing.argtypes = [ctypes.c_int]
@@ -105,6 +107,25 @@ def stim_detector_sample(handle: int, seed: int, shot_offset: int, num_shots: in
                          stream=None):
     _check(lib().stim_detector_sample(ctypes.c_void_p(handle), seed, shot_offset, num_shots,
                                       _dptr(out_det), _dptr(out_obs), _stream_ptr(stream)))
+
+
+def stim_sparse_detector_sample(handle: int, seed: int, shot_offset: int, num_shots: int, out_det,
+                                out_obs=None, stream=None):
+    _check(lib().stim_sparse_detector_sample(ctypes.c_void_p(handle), seed, shot_offset, num_shots,
+                                             _dptr(out_det), _dptr(out_obs), _stream_ptr(stream)))
+
+
+def stim_error_sets(handle: int):
+    """(offsets, lanes) as numpy uint32 arrays (host only)."""
+    import numpy as np
+    n_sets, n_ent = ctypes.c_uint64(), ctypes.c_uint64()
+    h = ctypes.c_void_p(handle)
+    _check(lib().stim_error_sets(h, ctypes.byref(n_sets), ctypes.byref(n_ent), None, None))
+    off = np.zeros(n_sets.value + 1, dtype=np.uint32)
+    lanes = np.zeros(max(n_ent.value, 1), dtype=np.uint32)
+    _check(lib().stim_error_sets(h, ctypes.byref(n_sets), ctypes.byref(n_ent), ctypes.c_void_p(off.ctypes.data),
+                                 ctypes.c_void_p(lanes.ctypes.data)))
+    return off, lanes[: n_ent.value]
 
 
 def stim_batch_sample(requests, stream=None):
@@ -197,3 +218,15 @@ class Circuit:
         o = torch.empty((self.num_observables, W), dtype=torch.int64, device="cuda") if obs else None
         stim_detector_sample(self.handle, seed, shot_offset, num_shots, det, o, stream)
         return det, o
+
+    def detect_sparse(self, seed: int, num_shots: int, shot_offset: int = 0, obs: bool = True, stream=None):
+        """Same results as detect(), by sparse detection-event sampling."""
+        import torch
+        W = (num_shots + 63) // 64
+        det = torch.empty((self.num_detectors, W), dtype=torch.int64, device="cuda")
+        o = torch.empty((self.num_observables, W), dtype=torch.int64, device="cuda") if obs else None
+        stim_sparse_detector_sample(self.handle, seed, shot_offset, num_shots, det, o, stream)
+        return det, o
+
+    def error_sets(self):
+        return stim_error_sets(self.handle)

@@ -1,0 +1,96 @@
+"""GPU: sparse detection-event sampling against the frame sampler and the
+oracle, bit for bit (both draw the same errors; detectors are deterministic)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_02202_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_2103_02202_amd import stim_gpu
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    stim_gpu.lib()
+    return stim_gpu
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("p", [1e-4, 1e-3, 1e-2, 0.3])
+@pytest.mark.parametrize("d,shots,offset", [(3, 1000, 0), (5, 4097, 64), (7, 20000, 1 << 30)])
+def test_sparse_matches_frame_and_oracle(sg, d, shots, offset, p):
+    announce("sparse surface", d, shots, offset, p)
+    text = wl.surface_code(d, d, p)
+    c, o = sg.Circuit(text), oracle.Circuit(text)
+    det, obs = c.detect_sparse(9, shots, shot_offset=offset)
+    fdet, fobs = c.detect(9, shots, shot_offset=offset)
+    torch.cuda.synchronize()
+    assert torch.equal(det, fdet) and torch.equal(obs, fobs)
+    want = o.sample(9, offset, shots, meas=False, det=True, obs=True)
+    assert np.array_equal(host(det), want["det"]) and np.array_equal(host(obs), want["obs"])
+
+
+def test_sparse_repetition_code_and_no_observable_output(sg):
+    announce("sparse repetition")
+    body = ("X_ERROR(0.05) 0 1 2 3 4 5 6 7 8 9 10\nCNOT 0 1 2 3 4 5 6 7 8 9\n"
+            "CNOT 10 9 8 7 6 5 4 3 2 1\nDEPOLARIZE2(0.02) 0 1 2 3\nMR 1 3 5 7 9\n")
+    first = "".join(f"DETECTOR rec[-{k}]\n" for k in range(1, 6))
+    later = "".join(f"DETECTOR rec[-{k}] rec[-{k + 5}]\n" for k in range(1, 6))
+    text = body + first + "REPEAT 30 {\n" + body + later + "}\nM 0 10\nOBSERVABLE_INCLUDE(0) rec[-1]\n"
+    c = sg.Circuit(text)
+    det, _ = c.detect_sparse(5, 3333, obs=False)
+    fdet, _ = c.detect(5, 3333, obs=False)
+    torch.cuda.synchronize()
+    assert torch.equal(det, fdet)
+    want = oracle.Circuit(text).sample(5, 0, 3333, meas=False, det=True)["det"]
+    assert np.array_equal(host(det), want)
+
+
+def test_sparse_refuses_unservable_circuits(sg):
+    announce("sparse refusals")
+    for text in ["H 0\nM 0\nDETECTOR rec[-1]\n", wl.surface_code(3, 3, 0.01, feedback_reset=True)]:
+        c = sg.Circuit(text)
+        with pytest.raises(sg.StimError) as e:
+            c.detect_sparse(0, 64)
+        assert e.value.code == sg.STIM_E_UNSUPPORTED
+
+
+def test_sparse_d15_full_run_equals_frame(sg):
+    announce("sparse d15 2^20 shots")
+    c = sg.Circuit(wl.surface_code(15, 15, 1e-3))
+    det, obs = c.detect_sparse(2, 1 << 20)
+    fdet, fobs = c.detect(2, 1 << 20)
+    torch.cuda.synchronize()
+    assert torch.equal(det, fdet) and torch.equal(obs, fobs)
+    assert int(torch.count_nonzero(det)) > 0
+
+
+@pytest.mark.parametrize("p", [1e-4, 1e-3])
+def test_sparse_d49_equals_frame_and_oracle_slices(sg, p):
+    announce("sparse d49", p)
+    text = wl.surface_code(49, 49, p)
+    c = sg.Circuit(text)
+    shots = 65536
+    det, obs = c.detect_sparse(0, shots)
+    fdet, fobs = c.detect(0, shots)
+    torch.cuda.synchronize()
+    assert torch.equal(det, fdet) and torch.equal(obs, fobs)
+    o = oracle.Circuit(text)
+    for w0 in (0, 1023):
+        want = o.sample(0, 64 * w0, 64, meas=False, det=True, obs=True)
+        assert np.array_equal(host(det[:, w0:w0 + 1]), want["det"])
+        assert np.array_equal(host(obs[:, w0:w0 + 1]), want["obs"])
