@@ -179,6 +179,34 @@ def bench_feedback(steps: int, det, obs, stream):
             "shot_gates_per_s": circ.num_gate_targets * SHOTS / dt}
 
 
+def bench_sparse(steps: int, det, obs, stream):
+    """Sparse detection-event sampling (identical events) on the d=49 workload
+    at p = 1e-3 and 1e-4, beside the frame path at the same p."""
+    import torch
+    from paper_2103_02202_amd import stim_gpu, workloads
+    out = {}
+    for p in (P, P / 10):
+        circ = stim_gpu.Circuit(workloads.surface_code(D, ROUNDS, p))
+        t0 = time.perf_counter()
+        circ.error_sets()
+        sets_s = time.perf_counter() - t0
+        entry = {"error_sets_s": sets_s}
+        for name, fn in (("sparse", stim_gpu.stim_sparse_detector_sample), ("frame", stim_gpu.stim_detector_sample)):
+            for _ in range(2):
+                fn(circ.handle, SEED, 0, SHOTS, det, obs, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn(circ.handle, SEED, 0, SHOTS, det, obs, stream)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            entry[name + "_ms"] = dt * 1e3
+            entry[name + "_shot_gates_per_s"] = circ.num_gate_targets * SHOTS / dt
+        entry["sparse_speedup"] = entry["frame_ms"] / entry["sparse_ms"]
+        out[f"p={p:g}"] = entry
+    return out
+
+
 def bench_serving(rates=(10, 30, 100, 300, 1000)):
     import torch
     from paper_2103_02202_amd import serve, workloads
@@ -222,6 +250,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-formats", action="store_true")
     ap.add_argument("--no-feedback", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--sparse-probe", type=float, default=None, metavar="P",
+                    help="only run sparse detection sampling of the d=49 workload at noise P, 5 times "
+                         "(for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -241,6 +273,18 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
+
+    if args.sparse_probe is not None:
+        circ = stim_gpu.Circuit(workloads.surface_code(D, ROUNDS, args.sparse_probe))
+        circ.error_sets()
+        W = (SHOTS + 63) // 64
+        det = torch.empty((circ.num_detectors, W), dtype=torch.int64, device="cuda")
+        obs = torch.empty((max(circ.num_observables, 1), W), dtype=torch.int64, device="cuda")
+        for _ in range(5):
+            stim_gpu.stim_sparse_detector_sample(circ.handle, SEED, 0, SHOTS, det, obs)
+        torch.cuda.synchronize()
+        print(json.dumps({"sparse_probe_p": args.sparse_probe, "calls": 5}), flush=True)
         return
 
     text = workloads.surface_code(D, ROUNDS, P)
@@ -333,6 +377,8 @@ def main():
         out["formats"] = bench_formats(det, meas, Dn, M, SHOTS)
     if not args.no_feedback:
         out["feedback"] = bench_feedback(max(3, args.steps // 2), det, obs, stream)
+    if not args.no_sparse:
+        out["sparse"] = bench_sparse(max(3, args.steps // 2), det, obs, stream)
     if not args.no_batch:
         out["batch"] = bench_batch(max(3, args.steps // 2))
     if not args.no_serving:

@@ -45,6 +45,7 @@ struct DeviceCopy {
   // Error sets of sparse detection sampling (uploaded on its first use).
   uint64_t *gen_base = nullptr;
   uint32_t *set_off = nullptr, *set_lanes = nullptr;
+  uint32_t *wb_e0 = nullptr, *wb_e1 = nullptr, *wb_base = nullptr;   // window batches
 };
 
 }  // namespace
@@ -63,6 +64,11 @@ struct stim_circuit {
   std::string em_msg;
   ErrorModel em;
   uint32_t em_max_groups = 0;     // most 32-slot groups of one noise execution
+  // Windowed sparse kernel: tile width (0: use the global-atomic kernel),
+  // window rows and the batches of noise executions.
+  int win_T = 0;
+  uint32_t win_rows = 0;
+  std::vector<uint32_t> wb_e0, wb_e1, wb_base;
 };
 
 namespace {
@@ -137,6 +143,8 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
   return STIM_OK;
 }
 
+void plan_window(stim_circuit *c);
+
 int ensure_error_model(stim_circuit *c) {
   if (!c->have_em) {
     c->have_em = true;
@@ -148,6 +156,7 @@ int ensure_error_model(stim_circuit *c) {
         const uint32_t groups = ((op.slot0 + op.n - 1) >> 5) - (op.slot0 >> 5) + 1;
         c->em_max_groups = std::max(c->em_max_groups, groups);
       }
+      plan_window(c);
     } catch (const CompileError &e) {
       c->em_code = e.code;
       c->em_msg = e.msg;
@@ -159,12 +168,98 @@ int ensure_error_model(stim_circuit *c) {
   return c->em_code ? set_error(c->em_code, c->em_msg) : STIM_OK;
 }
 
+// Plans the windowed sparse kernel: batches of consecutive noise executions
+// such that, before a batch, every detector row below its base is final (no
+// later execution touches it) and every row touched so far but not final
+// fits in the window.  Tries T = 2, then T = 1; leaves win_T = 0 when the
+// window does not fit (the global-atomic kernel is used instead).
+//
+// Choice between the two kernels: the windowed one writes every output word
+// once from LDS but pays per-batch barriers and 16-byte row pieces; the
+// global one zeroes the outputs at full bandwidth and then pays one global
+// atomic per (error, flipped output).  The second wins when the expected
+// flipped outputs per shot are a small fraction of the detectors: below
+// kWindowMinDensity the global kernel is used.  STIM_SPARSE_WINDOW = 0 / 1
+// forces either kernel.
+constexpr double kWindowMinDensity = 0.005;
+
+void plan_window(stim_circuit *c) {
+  c->win_T = 0;
+  const char *env = std::getenv("STIM_SPARSE_WINDOW");
+  if (env && std::atoi(env) == 0) return;
+  const bool forced = env && std::atoi(env) == 1;
+  const Program &P = c->prog;
+  const ErrorModel &em = c->em;
+  const uint64_t D = P.num_detectors, L = P.num_observables;
+  if (L > kWindowMaxObs || D >= (1ull << 31)) return;
+  const size_t E = em.gen_base.size();
+  std::vector<int64_t> lo(E, (int64_t)D), hi(E, -1);
+  double flips_per_shot = 0;
+  for (size_t e = 0; e < E; e++) {
+    const uint64_t g1 = e + 1 < E ? em.gen_base[e + 1] : em.num_generators;
+    const DevOp &op = P.ops[P.noise_pc[e]];
+    const double pe = (double)(0ull - P.thresholds[(size_t)op.aux * 64]) * 0x1p-64;
+    // An error activates about half of its site's generators.
+    flips_per_shot += pe * 0.5 * (double)(em.set_off[g1] - em.set_off[em.gen_base[e]]);
+    for (uint64_t a = em.set_off[em.gen_base[e]]; a < em.set_off[g1]; a++) {
+      const int64_t l = em.set_lanes[a];
+      if (l >= (int64_t)D) continue;
+      lo[e] = std::min(lo[e], l);
+      hi[e] = std::max(hi[e], l);
+    }
+  }
+  if (!forced && flips_per_shot < kWindowMinDensity * (double)std::max<uint64_t>(D, 1)) return;
+  std::vector<int64_t> suf(E + 1, (int64_t)D);
+  for (size_t e = E; e-- > 0;) suf[e] = std::min(suf[e + 1], lo[e]);
+  int order[2] = {2, 1};
+  if (const char *t = std::getenv("STIM_SPARSE_T")) {
+    const int v = std::atoi(t);
+    if (v == 1 || v == 2) order[0] = order[1] = v;
+  }
+  for (int T : order) {
+    const int64_t cap = sparse_window_max_rows(T, (uint32_t)L);
+    if (cap <= 0) continue;
+    std::vector<uint32_t> e0s, e1s, bases;
+    int64_t H = -1, need = 1;
+    bool ok = true;
+    for (size_t e = 0; e < E && ok;) {
+      const int64_t base = suf[e];
+      size_t e1 = e;
+      int64_t Hb = H;
+      while (e1 < E && e1 - e < kWindowMaxExec) {
+        const int64_t h = std::max(Hb, hi[e1]);
+        if (h >= base && h - base + 1 > cap) break;
+        Hb = h;
+        e1++;
+      }
+      if (e1 == e) ok = false;
+      else {
+        if (Hb >= base) need = std::max(need, Hb - base + 1);
+        e0s.push_back((uint32_t)e);
+        e1s.push_back((uint32_t)e1);
+        bases.push_back((uint32_t)base);
+        H = Hb;
+        e = e1;
+      }
+    }
+    if (!ok) continue;
+    c->win_T = T;
+    c->win_rows = (uint32_t)need;
+    c->wb_e0 = std::move(e0s);
+    c->wb_e1 = std::move(e1s);
+    c->wb_base = std::move(bases);
+    return;
+  }
+}
+
 int ensure_sparse_device(stim_circuit *c, DeviceCopy *d, hipStream_t s) {
   if (d->set_off) return STIM_OK;
   hipError_t e;
   if ((e = upload(c->em.gen_base, &d->gen_base, s)) != hipSuccess ||
       (e = upload(c->em.set_off, &d->set_off, s)) != hipSuccess ||
-      (e = upload(c->em.set_lanes, &d->set_lanes, s)) != hipSuccess)
+      (e = upload(c->em.set_lanes, &d->set_lanes, s)) != hipSuccess ||
+      (e = upload(c->wb_e0, &d->wb_e0, s)) != hipSuccess || (e = upload(c->wb_e1, &d->wb_e1, s)) != hipSuccess ||
+      (e = upload(c->wb_base, &d->wb_base, s)) != hipSuccess)
     return e == hipErrorOutOfMemory ? set_error(STIM_E_OOM, "device allocation failed") : hip_error(e, "upload");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   return STIM_OK;
@@ -828,7 +923,8 @@ void stim_circuit_free(stim_circuit *c) {
     DeviceCopy &d = kv.second;
     void *ptrs[] = {d.ops,       d.targets,     d.thresholds, d.ref,     d.det_off,
                     d.det_idx,   d.obs_off,     d.obs_idx,    d.det_order, d.noise_pc,
-                    d.noise_instr, d.gen_base, d.set_off,    d.set_lanes};
+                    d.noise_instr, d.gen_base, d.set_off,    d.set_lanes, d.wb_e0,
+                    d.wb_e1,       d.wb_base};
     for (void *p : ptrs) if (p) (void)hipFree(p);
   }
   if (!c->dev.empty()) (void)hipSetDevice(cur);
@@ -925,11 +1021,6 @@ int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_of
   }
   const Program &P = c->prog;
   hipError_t e;
-  if (P.num_detectors && (e = hipMemsetAsync(out_det, 0, P.num_detectors * W * sizeof(uint64_t), s)) != hipSuccess)
-    return hip_error(e, "hipMemsetAsync");
-  if (out_obs && P.num_observables &&
-      (e = hipMemsetAsync(out_obs, 0, P.num_observables * W * sizeof(uint64_t), s)) != hipSuccess)
-    return hip_error(e, "hipMemsetAsync");
   SparseParams sp{};
   sp.ops = d->ops;
   sp.targets = d->targets;
@@ -946,6 +1037,24 @@ int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_of
   sp.det = out_det;
   sp.obs = P.num_observables ? out_obs : nullptr;
   sp.num_det = (uint32_t)P.num_detectors;
+  if (c->win_T) {
+    // Windowed kernel: every output word is written exactly once.
+    SparseWindowParams wp{};
+    wp.s = sp;
+    wp.batch_e0 = d->wb_e0;
+    wp.batch_e1 = d->wb_e1;
+    wp.batch_base = d->wb_base;
+    wp.num_batches = (uint32_t)c->wb_e0.size();
+    wp.win = c->win_rows;
+    wp.num_obs = (uint32_t)P.num_observables;
+    if ((e = launch_sparse_window(wp, c->win_T, s)) != hipSuccess) return hip_error(e, "sparse window kernel launch");
+    return STIM_OK;
+  }
+  if (P.num_detectors && (e = hipMemsetAsync(out_det, 0, P.num_detectors * W * sizeof(uint64_t), s)) != hipSuccess)
+    return hip_error(e, "hipMemsetAsync");
+  if (out_obs && P.num_observables &&
+      (e = hipMemsetAsync(out_obs, 0, P.num_observables * W * sizeof(uint64_t), s)) != hipSuccess)
+    return hip_error(e, "hipMemsetAsync");
   if ((e = launch_sparse_events(sp, (uint32_t)P.noise_pc.size(), (uint64_t)c->em_max_groups * W, s)) != hipSuccess)
     return hip_error(e, "sparse event kernel launch");
   return STIM_OK;

@@ -34,4 +34,30 @@ constexpr uint32_t kSparseChunk = 2048;
 hipError_t launch_sparse_events(const SparseParams &p, uint32_t instances, uint64_t max_candidates,
                                 hipStream_t stream);
 
+// Windowed variant: one workgroup per tile of T words (T = 1 or 2) walks
+// the noise executions in circuit order, in batches, and accumulates its
+// detection events in an LDS window of `win` detector rows (a ring), writing
+// each row to det once it can no longer change (plain stores, no atomics, no
+// zeroing of det).  Batch b covers executions [batch_e0[b], batch_e1[b]); all
+// rows below batch_base[b] are final before it starts, and every row its
+// errors touch lies in [batch_base[b], batch_base[b] + win).  Observables
+// (at most kWindowMaxObs) are accumulated in LDS too.
+constexpr uint32_t kWindowThreads = 1024;
+constexpr uint32_t kWindowMaxExec = 32;      // executions per batch
+constexpr uint32_t kWindowMaxObs = 256;
+
+struct SparseWindowParams {
+  SparseParams s;
+  const uint32_t *batch_e0, *batch_e1, *batch_base;
+  uint32_t num_batches;
+  uint32_t win;
+  uint32_t num_obs;
+};
+
+// Dynamic LDS bytes of one windowed workgroup, and the most window rows that
+// fit next to the static part.
+size_t sparse_window_lds_bytes(int T, uint32_t win, uint32_t num_obs);
+uint32_t sparse_window_max_rows(int T, uint32_t num_obs);
+hipError_t launch_sparse_window(const SparseWindowParams &p, int T, hipStream_t stream);
+
 }  // namespace stimgpu

@@ -30,10 +30,18 @@ def host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
+PATHS = {"window": {"STIM_SPARSE_WINDOW": "1"}, "window_T1": {"STIM_SPARSE_WINDOW": "1", "STIM_SPARSE_T": "1"},
+         "global": {"STIM_SPARSE_WINDOW": "0"}}
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("p", [1e-4, 1e-3, 1e-2, 0.3])
 @pytest.mark.parametrize("d,shots,offset", [(3, 1000, 0), (5, 4097, 64), (7, 20000, 1 << 30)])
-def test_sparse_matches_frame_and_oracle(sg, d, shots, offset, p):
-    announce("sparse surface", d, shots, offset, p)
+def test_sparse_matches_frame_and_oracle(sg, d, shots, offset, p, path, monkeypatch):
+    """The windowed kernel (tile width 2 or 1) and the global-atomic kernel."""
+    for k, v in PATHS[path].items():
+        monkeypatch.setenv(k, v)
+    announce("sparse surface", path, d, shots, offset, p)
     text = wl.surface_code(d, d, p)
     c, o = sg.Circuit(text), oracle.Circuit(text)
     det, obs = c.detect_sparse(9, shots, shot_offset=offset)
@@ -94,3 +102,21 @@ def test_sparse_d49_equals_frame_and_oracle_slices(sg, p):
         want = o.sample(0, 64 * w0, 64, meas=False, det=True, obs=True)
         assert np.array_equal(host(det[:, w0:w0 + 1]), want["det"])
         assert np.array_equal(host(obs[:, w0:w0 + 1]), want["obs"])
+
+
+@pytest.mark.parametrize("text", [
+    # An early error flips the first and the last detector: no window fits.
+    "X_ERROR(0.05) 0\nM 0\nDETECTOR rec[-1]\nREPEAT 20000 {\n  X_ERROR(0.01) 1\n  M 1\n  DETECTOR rec[-1]\n}\n"
+    "M 0\nDETECTOR rec[-1]\n",
+    # More observables than the window kernel keeps in LDS.
+    "X_ERROR(0.05) " + " ".join(map(str, range(300))) + "\nM " + " ".join(map(str, range(300))) + "\n"
+    + "".join(f"OBSERVABLE_INCLUDE({k}) rec[-{300 - k}]\n" for k in range(300)),
+])
+def test_sparse_falls_back_when_no_window_fits(sg, text):
+    announce("sparse fallback", len(text))
+    c = sg.Circuit(text)
+    det, obs = c.detect_sparse(3, 3000)
+    fdet, fobs = c.detect(3, 3000)
+    torch.cuda.synchronize()
+    assert torch.equal(det, fdet) and torch.equal(obs, fobs)
+    assert int(torch.count_nonzero(det)) + int(torch.count_nonzero(obs)) > 0
