@@ -92,6 +92,16 @@ int stim_circuit_shape(const stim_circuit *c, uint64_t *num_qubits, uint64_t *nu
  * to only compute and cache. */
 int stim_reference_sample(stim_circuit *c, uint64_t *ref_out);
 
+/* The same canonical reference sample computed on the GPU (Sec. 4 with the
+ * inverse tableau in device memory: one wave per target for each Clifford
+ * layer, deterministic results of a measurement layer read in parallel, the
+ * random ones collapsed in order by one workgroup).  Always recomputes; the
+ * result is cached in the handle if none is.  ref_out: host buffer as for
+ * stim_reference_sample, or NULL.  Runs on `hip_stream` and waits for it.
+ * The sampling calls use this path by themselves for circuits of 1,024 or
+ * more qubits (environment STIM_GPU_REFERENCE = 0 / 1 forces host / GPU). */
+int stim_reference_sample_gpu(stim_circuit *c, uint64_t *ref_out, void *hip_stream);
+
 /* Samples measurement records of shots [shot_offset, shot_offset + num_shots)
  * (Sec. 3).  out_meas: device buffer [num_measurements][W] uint64.
  * shot_offset must be a multiple of 64; num_shots > 0.  Computes the reference

@@ -17,7 +17,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["circuit.cpp", "reference.cpp", "error_sets.cpp"]
-HIP_SOURCES = ["frame_kernels.hip", "format_kernels.hip", "sparse_kernels.hip", "capi.hip"]
+HIP_SOURCES = ["frame_kernels.hip", "format_kernels.hip", "sparse_kernels.hip", "reference_gpu.hip", "capi.hip"]
 
 # Packed-FP32 instructions are kept out of every HIP object.
 # Private arrays must not be promoted into LDS: the frame slice uses it all.

@@ -16,6 +16,7 @@
 #include "circuit.h"
 #include "format_kernels.h"
 #include "frame_kernels.h"
+#include "reference_gpu.h"
 #include "sparse_kernels.h"
 
 using namespace stimgpu;
@@ -83,8 +84,24 @@ hipError_t upload(const V &host, typename V::value_type **dst, hipStream_t s) {
   return e;
 }
 
-int ensure_reference(stim_circuit *c) {
+// Circuits with at least this many qubits compute their reference sample on
+// the GPU when a sampling call first needs it (STIM_GPU_REFERENCE = 0 / 1
+// forces the host / the GPU).
+constexpr uint64_t kGpuReferenceMinQubits = 1024;
+
+int ensure_reference(stim_circuit *c, hipStream_t s = nullptr, bool allow_gpu = false) {
   if (c->have_ref) return STIM_OK;
+  bool gpu = allow_gpu && c->prog.num_qubits >= kGpuReferenceMinQubits;
+  if (const char *env = std::getenv("STIM_GPU_REFERENCE")) gpu = allow_gpu && std::atoi(env) != 0;
+  if (gpu) {
+    std::string err;
+    std::vector<uint64_t> bits;
+    const int rc = gpu_reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements, bits, s, err);
+    if (rc) return set_error(rc, err);
+    c->ref = std::move(bits);
+    c->have_ref = true;
+    return STIM_OK;
+  }
   try {
     c->ref = reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements);
   } catch (const std::bad_alloc &) {
@@ -961,7 +978,7 @@ int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint
   DeviceCopy *d = nullptr;
   {
     std::lock_guard<std::mutex> lock(c->mu);
-    if ((rc = ensure_reference(c))) return rc;
+    if ((rc = ensure_reference(c, s, true))) return rc;
     if ((rc = ensure_device(c, s, &d))) return rc;
   }
   return run_frame(c, d, seed, shot_offset, num_shots, d->ref, out_meas, s);
@@ -979,7 +996,7 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   DeviceCopy *d = nullptr;
   {
     std::lock_guard<std::mutex> lock(c->mu);
-    if ((rc = ensure_reference(c))) return rc;
+    if ((rc = ensure_reference(c, s, true))) return rc;
     if ((rc = ensure_device(c, s, &d))) return rc;
   }
   const uint64_t W = (num_shots + 63) / 64;
@@ -1015,7 +1032,7 @@ int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_of
   {
     std::lock_guard<std::mutex> lock(c->mu);
     if ((rc = ensure_error_model(c))) return rc;
-    if ((rc = ensure_reference(c))) return rc;
+    if ((rc = ensure_reference(c, s, true))) return rc;
     if ((rc = ensure_device(c, s, &d))) return rc;
     if ((rc = ensure_sparse_device(c, d, s))) return rc;
   }
@@ -1057,6 +1074,23 @@ int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_of
     return hip_error(e, "hipMemsetAsync");
   if ((e = launch_sparse_events(sp, (uint32_t)P.noise_pc.size(), (uint64_t)c->em_max_groups * W, s)) != hipSuccess)
     return hip_error(e, "sparse event kernel launch");
+  return STIM_OK;
+}
+
+int stim_reference_sample_gpu(stim_circuit *c, uint64_t *ref_out, void *hip_stream) {
+  if (!c) return set_error(STIM_E_INVALID_ARG, "null circuit handle");
+  if (c->prog.max_loop_depth > 8) return set_error(STIM_E_UNSUPPORTED, "REPEAT nesting deeper than 8");
+  std::lock_guard<std::mutex> lock(c->mu);
+  std::string err;
+  std::vector<uint64_t> bits;
+  const int rc = gpu_reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements, bits,
+                                      (hipStream_t)hip_stream, err);
+  if (rc) return set_error(rc, err);
+  if (ref_out && !bits.empty()) std::memcpy(ref_out, bits.data(), bits.size() * sizeof(uint64_t));
+  if (!c->have_ref) {
+    c->ref = std::move(bits);
+    c->have_ref = true;
+  }
   return STIM_OK;
 }
 

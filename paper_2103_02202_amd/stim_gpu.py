@@ -47,6 +47,7 @@ def lib():
         L.stim_frame_sample.argtypes = [vp, u64, u64, u64, vp, vp]
         L.stim_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.stim_sparse_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
+        L.stim_reference_sample_gpu.argtypes = [vp, vp, vp]
         L.stim_error_sets.argtypes = [vp, P64, P64, vp, vp]
         L.stim_batch_sample.argtypes = [ctypes.POINTER(StimRequest), ctypes.c_size_t, vp]
         L.stim_format_shots.argtypes = [vp, u64, u64, ctypes.c_int, vp, u64, P64, vp]
@@ -95,6 +96,15 @@ def stim_reference_sample(handle: int, num_measurements: int):
     n = max((num_measurements + 63) // 64, 1)
     buf = (ctypes.c_uint64 * n)()
     _check(lib().stim_reference_sample(ctypes.c_void_p(handle), ctypes.cast(buf, ctypes.c_void_p)))
+    return [int(x) for x in buf][: (num_measurements + 63) // 64]
+
+
+def stim_reference_sample_gpu(handle: int, num_measurements: int, stream=None):
+    """Reference bits computed on the GPU, as a list of uint64 words."""
+    n = max((num_measurements + 63) // 64, 1)
+    buf = (ctypes.c_uint64 * n)()
+    _check(lib().stim_reference_sample_gpu(ctypes.c_void_p(handle), ctypes.cast(buf, ctypes.c_void_p),
+                                           _stream_ptr(stream)))
     return [int(x) for x in buf][: (num_measurements + 63) // 64]
 
 
@@ -230,3 +240,7 @@ class Circuit:
 
     def error_sets(self):
         return stim_error_sets(self.handle)
+
+    def reference_gpu(self, stream=None):
+        """Canonical reference sample computed on the GPU (uint64 words)."""
+        return stim_reference_sample_gpu(self.handle, self.num_measurements, stream)
