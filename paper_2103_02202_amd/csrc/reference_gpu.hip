@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "circuit.h"
+#include "format_kernels.h"
 #include "reference_gpu.h"
 #include "stim_gpu.h"
 
@@ -43,9 +44,9 @@ namespace stimgpu {
 namespace {
 
 struct Tab {
-  uint64_t *xb, *zb;     // [2n][nw]
-  uint32_t *sign;        // [2n]
-  uint32_t n, nw;
+  uint64_t *xb, *zb;     // by columns: [2n][nwp]
+  uint32_t *sb;          // signs, one bit per column (also read as 64-bit words)
+  uint32_t n, nw, nwp;   // qubits, words per column, column stride
 };
 
 enum StepKind : uint8_t { STEP_PREPEND, STEP_MEASURE, STEP_FEEDBACK };
@@ -63,9 +64,16 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t sign_of(const Tab &t, uint32_t c) { return (t.sb[c >> 5] >> (c & 31)) & 1u; }
+
+// Sign bits of different columns share words: updates are atomic.
+__device__ __forceinline__ void sign_xor(const Tab &t, uint32_t c, uint32_t v) {
+  if (v) atomicXor(t.sb + (c >> 5), 1u << (c & 31));
+}
+
 __device__ __forceinline__ void wave_swap_cols(const Tab &t, uint32_t a, uint32_t b, uint32_t lane) {
-  uint64_t *xa = t.xb + (size_t)a * t.nw, *xb = t.xb + (size_t)b * t.nw;
-  uint64_t *za = t.zb + (size_t)a * t.nw, *zb = t.zb + (size_t)b * t.nw;
+  uint64_t *xa = t.xb + (size_t)a * t.nwp, *xb = t.xb + (size_t)b * t.nwp;
+  uint64_t *za = t.zb + (size_t)a * t.nwp, *zb = t.zb + (size_t)b * t.nwp;
   for (uint32_t w = lane; w < t.nw; w += 64) {
     const uint64_t x = xa[w], z = za[w];
     xa[w] = xb[w];
@@ -74,9 +82,9 @@ __device__ __forceinline__ void wave_swap_cols(const Tab &t, uint32_t a, uint32_
     zb[w] = z;
   }
   if (lane == 0) {
-    const uint32_t s = t.sign[a];
-    t.sign[a] = t.sign[b];
-    t.sign[b] = s;
+    const uint32_t d = sign_of(t, a) ^ sign_of(t, b);
+    sign_xor(t, a, d);
+    sign_xor(t, b, d);
   }
 }
 
@@ -84,8 +92,8 @@ __device__ __forceinline__ void wave_swap_cols(const Tab &t, uint32_t a, uint32_
 // as i^(x z) X^x Z^z, the product's phase exponent is the sum over qubits of
 // x1 z1 + x2 z2 + 2 z1 x2 - x3 z3; it must be even (a real sign).
 __device__ __forceinline__ void wave_mul_cols(const Tab &t, uint32_t dst, uint32_t src, int e, uint32_t lane) {
-  uint64_t *x1 = t.xb + (size_t)dst * t.nw, *z1 = t.zb + (size_t)dst * t.nw;
-  const uint64_t *x2 = t.xb + (size_t)src * t.nw, *z2 = t.zb + (size_t)src * t.nw;
+  uint64_t *x1 = t.xb + (size_t)dst * t.nwp, *z1 = t.zb + (size_t)dst * t.nwp;
+  const uint64_t *x2 = t.xb + (size_t)src * t.nwp, *z2 = t.zb + (size_t)src * t.nwp;
   int acc = 0;
   for (uint32_t w = lane; w < t.nw; w += 64) {
     const uint64_t a = x1[w], b = z1[w], c = x2[w], d = z2[w];
@@ -95,11 +103,11 @@ __device__ __forceinline__ void wave_mul_cols(const Tab &t, uint32_t dst, uint32
     z1[w] = z3;
   }
   acc = wave_sum(acc) + e;
-  if (lane == 0) t.sign[dst] ^= t.sign[src] ^ (uint32_t)((acc >> 1) & 1);
+  if (lane == 0) sign_xor(t, dst, sign_of(t, src) ^ (uint32_t)((acc >> 1) & 1));
 }
 
 __device__ __forceinline__ void flip_sign(const Tab &t, uint32_t col, uint32_t lane) {
-  if (lane == 0) t.sign[col] ^= 1u;
+  if (lane == 0) sign_xor(t, col, 1u);
 }
 
 // Prepends the inverse of `gate` (T'(g) = T(G^dagger g G)), one wave per
@@ -142,119 +150,125 @@ __device__ __forceinline__ void set_ref_bit(uint64_t *ref, uint64_t m) {
 }
 
 // Deterministic results of a measurement step, one wave per target; random
-// targets are flagged for the ordered pass.
+// targets are flagged for the ordered pass and counted in *random.
 __global__ void __launch_bounds__(256) k_ref_measure_det(Tab t, Gate gate, const uint32_t *tg, uint32_t count,
-                                                         uint64_t meas0, uint64_t *ref, uint32_t *flag) {
+                                                         uint64_t meas0, uint64_t *ref, uint32_t *flag,
+                                                         uint32_t *random) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (k >= count) return;
   const uint32_t c = t.n + (tg[k] & TGT_QUBIT_MASK);
   bool any = false;
-  for (uint32_t w = lane; w < t.nw; w += 64) any |= t.xb[(size_t)c * t.nw + w] != 0;
+  for (uint32_t w = lane; w < t.nw; w += 64) any |= t.xb[(size_t)c * t.nwp + w] != 0;
   any = __any(any);
   if (lane == 0) {
     flag[k] = any ? 1u : 0u;
-    if (!any) {
-      if (gate != G_R && t.sign[c]) set_ref_bit(ref, meas0 + k);
-      if (gate != G_M) t.sign[c] = 0;
+    if (any) {
+      atomicAdd(random, 1u);
+    } else {
+      const uint32_t r = sign_of(t, c);
+      if (gate != G_R && r) set_ref_bit(ref, meas0 + k);
+      if (gate != G_M) sign_xor(t, c, r);      // reset: force the sign to +
     }
   }
 }
 
 constexpr uint32_t kRefThreads = 1024;
-constexpr uint32_t kRefMaxWords = 4096;     // n up to 262,144 qubits
+constexpr uint32_t kRefList = 8192;          // support rows gathered per round
 
-// The ordered pass over a measurement step's random targets (one workgroup).
-__global__ void __launch_bounds__(kRefThreads) k_ref_measure_rand(Tab t, Gate gate, const uint32_t *tg,
-                                                                   uint32_t count, uint64_t meas0, uint64_t *ref,
-                                                                   const uint32_t *flag) {
-  __shared__ uint64_t snap[kRefMaxWords];      // X part of the measured column
-  __shared__ uint32_t words[kRefMaxWords];     // indices of its non-zero words
-  __shared__ uint32_t s_pivot, s_bit, s_nwords;
-  const uint32_t tid = threadIdx.x, nw = t.nw, ncols = 2 * t.n;
+// The ordered pass over a measurement step's random targets, one workgroup,
+// on the transposed tableau: XR[j] / ZR[j] hold, for qubit j, the x / z bit
+// of every column (stride s2 words), and SB the column signs.  Appending a
+// gate at the start of time is then a few word-parallel row operations
+// (the reason the paper transposes for bursts of random measurements).
+__global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR, uint64_t *ZR, uint64_t *SB,
+                                                                    uint32_t n, uint32_t s2, Gate gate,
+                                                                    const uint32_t *tg, uint32_t count, uint64_t meas0,
+                                                                    uint64_t *ref, const uint32_t *flag) {
+  __shared__ uint32_t list[kRefList];
+  __shared__ uint32_t s_flag[kRefThreads * 4];
+  __shared__ uint32_t s_pivot, s_cnt, s_bit, s_more;
+  const uint32_t tid = threadIdx.x, words = (2 * n + 63) / 64;
   for (uint32_t k = 0; k < count; k++) {
-    if (!flag[k]) continue;                    // uniform
-    const uint32_t c = t.n + (tg[k] & TGT_QUBIT_MASK);
-    if (tid == 0) {
-      s_pivot = 0xFFFFFFFFu;
-      s_nwords = 0;
+    if (k % (kRefThreads * 4) == 0) {        // next chunk of flags, loaded in parallel
+      __syncthreads();
+      for (uint32_t i = tid; i < kRefThreads * 4 && k + i < count; i += blockDim.x) s_flag[i] = flag[k + i];
+      __syncthreads();
     }
+    if (!s_flag[k % (kRefThreads * 4)]) continue;   // uniform
+    const uint32_t c = n + (tg[k] & TGT_QUBIT_MASK);
+    const uint32_t cw = c >> 6;
+    const uint64_t cm = 1ull << (c & 63);
+    if (tid == 0) s_pivot = 0xFFFFFFFFu;
     __syncthreads();
-    for (uint32_t w = tid; w < nw; w += blockDim.x) {
-      const uint64_t v = t.xb[(size_t)c * nw + w];
-      snap[w] = v;
-      if (v) {
-        atomicMin(&s_pivot, w * 64 + (uint32_t)__builtin_ctzll(v));
-        words[atomicAdd(&s_nwords, 1u)] = w;
-      }
-    }
+    for (uint32_t j = tid; j < n; j += blockDim.x)
+      if (XR[(size_t)j * s2 + cw] & cm) atomicMin(&s_pivot, j);
     __syncthreads();
-    const uint32_t nwords = s_nwords;
-    const uint32_t pivot = s_pivot;
-    if (pivot == 0xFFFFFFFFu) {                // made deterministic by an earlier collapse
+    const uint32_t p = s_pivot;
+    if (p == 0xFFFFFFFFu) {                  // made deterministic by an earlier collapse
       if (tid == 0) {
-        if (gate != G_R && t.sign[c]) set_ref_bit(ref, meas0 + k);
-        if (gate != G_M) t.sign[c] = 0;
+        const bool r = (SB[cw] & cm) != 0;
+        if (gate != G_R && r) set_ref_bit(ref, meas0 + k);
+        if (gate != G_M && r) SB[cw] ^= cm;
       }
       __syncthreads();
       continue;
     }
-    const uint32_t pw = pivot >> 6;
-    const uint64_t pm = 1ull << (pivot & 63);
-    // CNOT appends from the pivot onto every other X/Y term, all columns
-    // (appends with a common control commute, so their order is free).
-    for (uint32_t col = tid; col < ncols; col += blockDim.x) {
-      uint64_t *X = t.xb + (size_t)col * nw, *Z = t.zb + (size_t)col * nw;
-      const uint64_t xp = (X[pw] & pm) ? 1 : 0;
-      uint64_t zp = (Z[pw] & pm) ? 1 : 0;
-      uint32_t s = 0;
-      for (uint32_t i = 0; i < nwords; i++) {
-        const uint32_t w = words[i];
-        uint64_t v = snap[w];
-        if (w == pw) v &= ~pm;
-        if (!v) continue;
-        uint64_t xw = X[w], zw = Z[w];
-        const uint64_t x0 = xw;
-        while (v) {
-          const uint32_t b = (uint32_t)__builtin_ctzll(v);
-          v &= v - 1;
-          const uint64_t xt = (xw >> b) & 1, zt = (zw >> b) & 1;
-          s ^= (uint32_t)(xp & zt & (xt ^ zp ^ 1));
-          xw ^= xp << b;
+    uint64_t *xp_row = XR + (size_t)p * s2, *zp_row = ZR + (size_t)p * s2;
+    // CNOT appends from the pivot onto every other row with an X/Y term in
+    // column c, gathered in rounds (an append clears the row's bit in c).
+    while (true) {
+      if (tid == 0) {
+        s_cnt = 0;
+        s_more = 0;
+      }
+      __syncthreads();
+      for (uint32_t j = tid; j < n; j += blockDim.x) {
+        if (j == p || !(XR[(size_t)j * s2 + cw] & cm)) continue;
+        const uint32_t i = atomicAdd(&s_cnt, 1u);
+        if (i < kRefList) list[i] = j;
+        else s_more = 1;
+      }
+      __syncthreads();
+      const uint32_t cnt = s_cnt < kRefList ? s_cnt : kRefList;
+      const bool more = s_more != 0;           // read before the next reset
+      if (cnt == 0) break;
+      for (uint32_t w = tid; w < words; w += blockDim.x) {
+        const uint64_t xp = xp_row[w];
+        uint64_t zp = zp_row[w], sb = SB[w];
+        for (uint32_t i = 0; i < cnt; i++) {
+          uint64_t *xt_p = XR + (size_t)list[i] * s2 + w;
+          const uint64_t xt = *xt_p, zt = ZR[(size_t)list[i] * s2 + w];
+          sb ^= xp & zt & ~(xt ^ zp);
+          *xt_p = xt ^ xp;
           zp ^= zt;
         }
-        if (xw != x0) X[w] = xw;
+        zp_row[w] = zp;
+        SB[w] = sb;
       }
-      const uint64_t zcur = (Z[pw] & pm) ? 1 : 0;
-      if (zcur != zp) Z[pw] ^= pm;
-      if (s) t.sign[col] ^= 1u;
+      __syncthreads();
+      if (!more) break;
     }
+    // H (X term at the pivot) or H_YZ (Y term) turns the column into +-Z_p.
+    if (tid == 0) s_bit = (zp_row[cw] & cm) ? 1u : 0u;
     __syncthreads();
-    if (tid == 0) s_bit = (t.zb[(size_t)c * nw + pw] & pm) ? 1u : 0u;
-    __syncthreads();
-    const bool yz = s_bit != 0;                // Y term at the pivot: H_YZ, else H
-    for (uint32_t col = tid; col < ncols; col += blockDim.x) {
-      uint64_t *X = t.xb + (size_t)col * nw + pw, *Z = t.zb + (size_t)col * nw + pw;
-      const uint64_t x = (*X & pm) ? 1 : 0, z = (*Z & pm) ? 1 : 0;
+    const bool yz = s_bit != 0;
+    for (uint32_t w = tid; w < words; w += blockDim.x) {
+      const uint64_t x = xp_row[w], z = zp_row[w];
       if (yz) {                                // X -> -X, Y -> Z, Z -> Y
-        if (x & (z ^ 1)) t.sign[col] ^= 1u;
-        if (z) *X ^= pm;
+        SB[w] ^= x & ~z;
+        xp_row[w] = x ^ z;
       } else {                                 // X <-> Z, Y -> -Y
-        if (x & z) t.sign[col] ^= 1u;
-        if (x ^ z) {
-          *X ^= pm;
-          *Z ^= pm;
-        }
+        SB[w] ^= x & z;
+        xp_row[w] = z;
+        zp_row[w] = x;
       }
     }
     __syncthreads();
-    if (tid == 0) s_bit = t.sign[c];
+    if (tid == 0) s_bit = (SB[cw] & cm) ? 1u : 0u;
     __syncthreads();
-    if (s_bit)                                 // X on the pivot makes the result 0
-      for (uint32_t col = tid; col < ncols; col += blockDim.x)
-        if (t.zb[(size_t)col * nw + pw] & pm) t.sign[col] ^= 1u;
-    __syncthreads();
-    if (tid == 0 && gate != G_M) t.sign[c] = 0;
+    if (s_bit)                                 // X on the pivot: the result becomes 0
+      for (uint32_t w = tid; w < words; w += blockDim.x) SB[w] ^= zp_row[w];
     __syncthreads();
   }
 }
@@ -268,15 +282,15 @@ __global__ void k_ref_feedback(Tab t, Gate gate, const uint32_t *tg, uint32_t co
   const uint32_t q = tg[2 * k];
   const uint64_t m = meas0 - tg[2 * k + 1];
   if (!((ref[m >> 6] >> (m & 63)) & 1)) return;
-  if (gate != G_CZ) t.sign[t.n + q] ^= 1u;     // X part flips T(Z_q)
-  if (gate != G_CX) t.sign[q] ^= 1u;           // Z part flips T(X_q)
+  if (gate != G_CZ) sign_xor(t, t.n + q, 1u);  // X part flips T(Z_q)
+  if (gate != G_CX) sign_xor(t, q, 1u);        // Z part flips T(X_q)
 }
 
 __global__ void k_ref_identity(Tab t) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= t.n) return;
-  t.xb[(size_t)q * t.nw + q / 64] = 1ull << (q % 64);
-  t.zb[(size_t)(t.n + q) * t.nw + q / 64] = 1ull << (q % 64);
+  t.xb[(size_t)q * t.nwp + q / 64] = 1ull << (q % 64);
+  t.zb[(size_t)(t.n + q) * t.nwp + q / 64] = 1ull << (q % 64);
 }
 
 __global__ void k_ref_zero(uint64_t *p, size_t n) {
@@ -360,34 +374,40 @@ int gpu_reference_sample(const std::vector<Node> &tree, uint64_t num_qubits, uin
                          std::vector<uint64_t> &bits, hipStream_t s, std::string &err) {
   bits.assign((num_measurements + 63) / 64, 0);
   if (num_measurements == 0) return STIM_OK;
-  const uint64_t n = num_qubits, nw = (n + 63) / 64;
-  if (nw > kRefMaxWords) {
+  const uint64_t n = num_qubits;
+  if (n >= (1ull << 30)) {
     err = "too many qubits for the GPU reference sampler";
     return STIM_E_UNSUPPORTED;
   }
   Planner P;
   P.walk(tree);
-  Tab t{nullptr, nullptr, nullptr, (uint32_t)n, (uint32_t)nw};
-  uint64_t *ref = nullptr;
-  uint32_t *dtg = nullptr, *flag = nullptr;
-  uint32_t max_meas_count = 1;
+  const uint64_t nw = (n + 63) / 64, nwp = transpose_stride(n);          // column stride
+  const uint64_t s2 = transpose_stride(2 * n);                           // row stride (transposed)
+  Tab t{nullptr, nullptr, nullptr, (uint32_t)n, (uint32_t)nw, (uint32_t)nwp};
+  uint64_t *ref = nullptr, *XR = nullptr, *ZR = nullptr;
+  uint32_t *dtg = nullptr, *flag = nullptr, *random = nullptr;
+  uint32_t max_meas_count = 1, nmeas_steps = 0;
   for (const Step &st : P.steps)
-    if (st.kind == STEP_MEASURE) max_meas_count = std::max(max_meas_count, st.count);
-  const size_t words = (size_t)2 * n * nw;
+    if (st.kind == STEP_MEASURE) {
+      max_meas_count = std::max(max_meas_count, st.count);
+      nmeas_steps++;
+    }
+  const size_t cwords = (size_t)2 * n * nwp, rwords = (size_t)n * s2;
   hipError_t e = hipSuccess;
   auto fail = [&](hipError_t code, const char *what) {
     err = std::string(what) + ": " + hipGetErrorString(code);
     return code == hipErrorOutOfMemory ? STIM_E_OOM : STIM_E_DEVICE;
   };
+  auto alloc = [&](void **ptr, size_t bytes) { return hipMallocAsync(ptr, std::max<size_t>(bytes, 8), s); };
   int rc = STIM_OK;
   do {
-    if ((e = hipMallocAsync((void **)&t.xb, words * 8, s)) != hipSuccess) { rc = fail(e, "tableau allocation"); break; }
-    if ((e = hipMallocAsync((void **)&t.zb, words * 8, s)) != hipSuccess) { rc = fail(e, "tableau allocation"); break; }
-    if ((e = hipMallocAsync((void **)&t.sign, 2 * n * 4 + 4, s)) != hipSuccess) { rc = fail(e, "tableau allocation"); break; }
-    if ((e = hipMallocAsync((void **)&ref, bits.size() * 8, s)) != hipSuccess) { rc = fail(e, "reference allocation"); break; }
-    if ((e = hipMallocAsync((void **)&flag, (size_t)max_meas_count * 4, s)) != hipSuccess) { rc = fail(e, "flag allocation"); break; }
-    if ((e = hipMallocAsync((void **)&dtg, std::max<size_t>(P.targets.size(), 1) * 4, s)) != hipSuccess) {
-      rc = fail(e, "target allocation");
+    if ((e = alloc((void **)&t.xb, cwords * 8)) != hipSuccess || (e = alloc((void **)&t.zb, cwords * 8)) != hipSuccess ||
+        (e = alloc((void **)&t.sb, s2 * 8)) != hipSuccess || (e = alloc((void **)&XR, rwords * 8)) != hipSuccess ||
+        (e = alloc((void **)&ZR, rwords * 8)) != hipSuccess || (e = alloc((void **)&ref, bits.size() * 8)) != hipSuccess ||
+        (e = alloc((void **)&flag, (size_t)max_meas_count * 4)) != hipSuccess ||
+        (e = alloc((void **)&random, (size_t)(std::max<uint32_t>(nmeas_steps, 1) + 1) / 2 * 8)) != hipSuccess ||
+        (e = alloc((void **)&dtg, P.targets.size() * 4)) != hipSuccess) {
+      rc = fail(e, "reference allocation");
       break;
     }
     if (!P.targets.empty() &&
@@ -395,26 +415,50 @@ int gpu_reference_sample(const std::vector<Node> &tree, uint64_t num_qubits, uin
       rc = fail(e, "target upload");
       break;
     }
-    hipLaunchKernelGGL(k_ref_zero, dim3(1024), dim3(256), 0, s, t.xb, words);
-    hipLaunchKernelGGL(k_ref_zero, dim3(1024), dim3(256), 0, s, t.zb, words);
-    hipLaunchKernelGGL(k_ref_zero, dim3(64), dim3(256), 0, s, (uint64_t *)t.sign, (size_t)(2 * n * 4 + 4) / 8);
+    hipLaunchKernelGGL(k_ref_zero, dim3(1024), dim3(256), 0, s, t.xb, cwords);
+    hipLaunchKernelGGL(k_ref_zero, dim3(1024), dim3(256), 0, s, t.zb, cwords);
+    hipLaunchKernelGGL(k_ref_zero, dim3(64), dim3(256), 0, s, (uint64_t *)t.sb, (size_t)s2);
     hipLaunchKernelGGL(k_ref_zero, dim3(64), dim3(256), 0, s, ref, bits.size());
+    hipLaunchKernelGGL(k_ref_zero, dim3(64), dim3(256), 0, s, (uint64_t *)random,
+                       (size_t)(std::max<uint32_t>(nmeas_steps, 1) + 1) / 2);
     hipLaunchKernelGGL(k_ref_identity, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, t);
+    uint32_t mstep = 0;
     for (const Step &st : P.steps) {
       if (st.count == 0) continue;
       const uint32_t *tg = dtg + st.toff;
       const dim3 waves((st.count + 3) / 4);
       if (st.kind == STEP_PREPEND) {
         hipLaunchKernelGGL(k_ref_prepend, waves, dim3(256), 0, s, t, st.gate, tg, st.count);
-      } else if (st.kind == STEP_MEASURE) {
-        hipLaunchKernelGGL(k_ref_measure_det, waves, dim3(256), 0, s, t, st.gate, tg, st.count, st.meas0, ref, flag);
-        hipLaunchKernelGGL(k_ref_measure_rand, dim3(1), dim3(kRefThreads), 0, s, t, st.gate, tg, st.count, st.meas0,
-                           ref, (const uint32_t *)flag);
-      } else {
+      } else if (st.kind == STEP_FEEDBACK) {
         hipLaunchKernelGGL(k_ref_feedback, dim3((st.count + 255) / 256), dim3(256), 0, s, t, st.gate, tg, st.count,
                            st.meas0, (const uint64_t *)ref);
+      } else {
+        uint32_t *rnd = random + mstep++;
+        hipLaunchKernelGGL(k_ref_measure_det, waves, dim3(256), 0, s, t, st.gate, tg, st.count, st.meas0, ref, flag,
+                           rnd);
+        uint32_t h_rnd = 0;
+        if ((e = hipMemcpyAsync(&h_rnd, rnd, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess) {
+          rc = fail(e, "reference measurement step");
+          break;
+        }
+        if (h_rnd == 0) continue;
+        // Random results: transpose, collapse them in order, transpose back.
+        if ((e = launch_transpose(t.xb, 2 * n, nwp, n, XR, s)) != hipSuccess ||
+            (e = launch_transpose(t.zb, 2 * n, nwp, n, ZR, s)) != hipSuccess) {
+          rc = fail(e, "tableau transpose");
+          break;
+        }
+        hipLaunchKernelGGL(k_ref_collapse_rows, dim3(1), dim3(kRefThreads), 0, s, XR, ZR, (uint64_t *)t.sb,
+                           (uint32_t)n, (uint32_t)s2, st.gate, tg, st.count, st.meas0, ref, (const uint32_t *)flag);
+        if ((e = launch_transpose(XR, n, s2, 2 * n, t.xb, s)) != hipSuccess ||
+            (e = launch_transpose(ZR, n, s2, 2 * n, t.zb, s)) != hipSuccess) {
+          rc = fail(e, "tableau transpose");
+          break;
+        }
       }
     }
+    if (rc) break;
     if ((e = hipGetLastError()) != hipSuccess) { rc = fail(e, "reference kernel launch"); break; }
     if ((e = hipMemcpyAsync(bits.data(), ref, bits.size() * 8, hipMemcpyDeviceToHost, s)) != hipSuccess) {
       rc = fail(e, "reference download");
@@ -422,7 +466,7 @@ int gpu_reference_sample(const std::vector<Node> &tree, uint64_t num_qubits, uin
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = fail(e, "reference kernels"); break; }
   } while (false);
-  void *ptrs[] = {t.xb, t.zb, t.sign, ref, flag, dtg};
+  void *ptrs[] = {t.xb, t.zb, t.sb, XR, ZR, ref, flag, random, dtg};
   for (void *p : ptrs)
     if (p) (void)hipFreeAsync(p, s);
   return rc;
