@@ -15,6 +15,12 @@ Prints one JSON line.  Fields beyond the driver's contract:
   meas_mode     -- measurement-record sampling (stim_frame_sample) rate
   formats       -- shot-major output formats (01, b8, hits, r8) of the run's
                    detection events and record: time and bytes per second
+  feedback      -- the same workload with ancillas reset by classically
+                   controlled X (M + CX rec[-k] a) instead of R
+  sparse        -- sparse detection-event sampling (identical events) at
+                   p = 1e-3 and 1e-4 beside the frame path
+  reference     -- canonical reference sample at d = 49 and 101: host
+                   inverse tableau vs the GPU tableau
   batch         -- the 64-circuit mix in one persistent graph-captured launch
                    vs the same requests one at a time
   serving       -- Poisson request streams over the resident d = 3..101 pool:
@@ -207,6 +213,29 @@ def bench_sparse(steps: int, det, obs, stream):
     return out
 
 
+def bench_reference():
+    """Canonical reference sample (Sec. 4) of the d=49 and d=101 surface codes:
+    host inverse tableau (one core) vs the GPU tableau; both must agree."""
+    import torch
+    from paper_2103_02202_amd import stim_gpu, workloads
+    out = {}
+    for d in (D, 101):
+        text = workloads.surface_code(d, d, P)
+        g = stim_gpu.Circuit(text)
+        g.reference_gpu()                       # warm-up (allocations, code load)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gpu_bits = g.reference_gpu()
+        gpu_s = time.perf_counter() - t0
+        h = stim_gpu.Circuit(text)
+        t0 = time.perf_counter()
+        host_bits = h.reference()
+        host_s = time.perf_counter() - t0
+        out[f"d={d}"] = {"qubits": g.num_qubits, "measurements": g.num_measurements, "host_s": host_s,
+                         "gpu_s": gpu_s, "speedup": host_s / gpu_s, "identical": gpu_bits == host_bits}
+    return out
+
+
 def bench_serving(rates=(10, 30, 100, 300, 1000)):
     import torch
     from paper_2103_02202_amd import serve, workloads
@@ -251,6 +280,7 @@ def main():
     ap.add_argument("--no-formats", action="store_true")
     ap.add_argument("--no-feedback", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--sparse-probe", type=float, default=None, metavar="P",
                     help="only run sparse detection sampling of the d=49 workload at noise P, 5 times "
                          "(for profiling)")
@@ -379,6 +409,8 @@ def main():
         out["feedback"] = bench_feedback(max(3, args.steps // 2), det, obs, stream)
     if not args.no_sparse:
         out["sparse"] = bench_sparse(max(3, args.steps // 2), det, obs, stream)
+    if not args.no_reference:
+        out["reference"] = bench_reference()
     if not args.no_batch:
         out["batch"] = bench_batch(max(3, args.steps // 2))
     if not args.no_serving:

@@ -199,10 +199,31 @@ __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR,
     const uint32_t c = n + (tg[k] & TGT_QUBIT_MASK);
     const uint32_t cw = c >> 6;
     const uint64_t cm = 1ull << (c & 63);
-    if (tid == 0) s_pivot = 0xFFFFFFFFu;
+    // One scan finds the pivot (lowest row with an X/Y term in column c)
+    // and gathers the first rows of the support.
+    if (tid == 0) {
+      s_pivot = 0xFFFFFFFFu;
+      s_cnt = 0;
+      s_more = 0;
+    }
     __syncthreads();
-    for (uint32_t j = tid; j < n; j += blockDim.x)
-      if (XR[(size_t)j * s2 + cw] & cm) atomicMin(&s_pivot, j);
+    for (uint32_t j0 = tid; j0 < n; j0 += 4 * blockDim.x) {
+      uint64_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t j = j0 + u * blockDim.x;
+        v[u] = j < n ? XR[(size_t)j * s2 + cw] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if (!(v[u] & cm)) continue;
+        const uint32_t j = j0 + u * blockDim.x;
+        atomicMin(&s_pivot, j);
+        const uint32_t i = atomicAdd(&s_cnt, 1u);
+        if (i < kRefList) list[i] = j;
+        else s_more = 1;
+      }
+    }
     __syncthreads();
     const uint32_t p = s_pivot;
     if (p == 0xFFFFFFFFu) {                  // made deterministic by an earlier collapse
@@ -216,29 +237,36 @@ __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR,
     }
     uint64_t *xp_row = XR + (size_t)p * s2, *zp_row = ZR + (size_t)p * s2;
     // CNOT appends from the pivot onto every other row with an X/Y term in
-    // column c, gathered in rounds (an append clears the row's bit in c).
+    // column c (the pivot's own entry in the list is skipped).  A support
+    // larger than the list is handled in rounds: an append clears the row's
+    // bit in column c, so a rescan finds the rest.
+    bool first_round = true;
     while (true) {
-      if (tid == 0) {
-        s_cnt = 0;
-        s_more = 0;
+      if (!first_round) {
+        if (tid == 0) {
+          s_cnt = 0;
+          s_more = 0;
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < n; j += blockDim.x) {
+          if (j == p || !(XR[(size_t)j * s2 + cw] & cm)) continue;
+          const uint32_t i = atomicAdd(&s_cnt, 1u);
+          if (i < kRefList) list[i] = j;
+          else s_more = 1;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      for (uint32_t j = tid; j < n; j += blockDim.x) {
-        if (j == p || !(XR[(size_t)j * s2 + cw] & cm)) continue;
-        const uint32_t i = atomicAdd(&s_cnt, 1u);
-        if (i < kRefList) list[i] = j;
-        else s_more = 1;
-      }
-      __syncthreads();
+      first_round = false;
       const uint32_t cnt = s_cnt < kRefList ? s_cnt : kRefList;
       const bool more = s_more != 0;           // read before the next reset
-      if (cnt == 0) break;
       for (uint32_t w = tid; w < words; w += blockDim.x) {
         const uint64_t xp = xp_row[w];
         uint64_t zp = zp_row[w], sb = SB[w];
         for (uint32_t i = 0; i < cnt; i++) {
-          uint64_t *xt_p = XR + (size_t)list[i] * s2 + w;
-          const uint64_t xt = *xt_p, zt = ZR[(size_t)list[i] * s2 + w];
+          const uint32_t r = list[i];
+          if (r == p) continue;
+          uint64_t *xt_p = XR + (size_t)r * s2 + w;
+          const uint64_t xt = *xt_p, zt = ZR[(size_t)r * s2 + w];
           sb ^= xp & zt & ~(xt ^ zp);
           *xt_p = xt ^ xp;
           zp ^= zt;
