@@ -284,6 +284,9 @@ def main():
     ap.add_argument("--sparse-probe", type=float, default=None, metavar="P",
                     help="only run sparse detection sampling of the d=49 workload at noise P, 5 times "
                          "(for profiling)")
+    ap.add_argument("--reference-probe", type=int, default=None, metavar="D",
+                    help="only compute the GPU reference sample of the distance-D surface code twice "
+                         "(for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -303,6 +306,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
+
+    if args.reference_probe is not None:
+        circ = stim_gpu.Circuit(workloads.surface_code(args.reference_probe, args.reference_probe, P))
+        for _ in range(2):
+            circ.reference_gpu()
+        print(json.dumps({"reference_probe_d": args.reference_probe, "calls": 2}), flush=True)
         return
 
     if args.sparse_probe is not None:

@@ -330,20 +330,36 @@ struct Planner {
   std::vector<Step> steps;
   std::vector<uint32_t> targets;
   uint64_t meas = 0;
+  // Run in which each value was last used (values: qubits, and lookbacks of
+  // feedback pairs, which at worst split a run more often than needed).
+  std::unordered_map<uint32_t, uint64_t> big_stamp;
+  std::vector<uint64_t> stamp;
+  uint64_t run_id = 0;
+
+  explicit Planner(uint64_t n) : stamp(n, ~0ull) {}
+
+  bool seen(uint32_t v) {
+    if (v < stamp.size()) return stamp[v] == run_id;
+    auto it = big_stamp.find(v);
+    return it != big_stamp.end() && it->second == run_id;
+  }
+  void mark(uint32_t v) {
+    if (v < stamp.size()) stamp[v] = run_id;
+    else big_stamp[v] = run_id;
+  }
 
   // Splits a target list (k per item) into runs of items with distinct qubits.
   void add_runs(StepKind kind, Gate gate, const std::vector<uint32_t> &t, size_t k) {
-    std::unordered_map<uint32_t, int> used;
     size_t i = 0;
     while (i < t.size() / k) {
-      used.clear();
+      run_id++;
       Step s{kind, gate, (uint32_t)targets.size(), 0, meas};
       while (i < t.size() / k) {
         bool clash = false;
-        for (size_t j = 0; j < k; j++) clash |= used.count(t[i * k + j] & TGT_QUBIT_MASK) > 0;
+        for (size_t j = 0; j < k; j++) clash |= seen(t[i * k + j] & TGT_QUBIT_MASK);
         if (clash) break;
         for (size_t j = 0; j < k; j++) {
-          used[t[i * k + j] & TGT_QUBIT_MASK] = 1;
+          mark(t[i * k + j] & TGT_QUBIT_MASK);
           targets.push_back(t[i * k + j]);
         }
         s.count++;
@@ -407,7 +423,7 @@ int gpu_reference_sample(const std::vector<Node> &tree, uint64_t num_qubits, uin
     err = "too many qubits for the GPU reference sampler";
     return STIM_E_UNSUPPORTED;
   }
-  Planner P;
+  Planner P(n);
   P.walk(tree);
   const uint64_t nw = (n + 63) / 64, nwp = transpose_stride(n);          // column stride
   const uint64_t s2 = transpose_stride(2 * n);                           // row stride (transposed)
