@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE all bytes written.  None when the kernels changed after the
 # counters were taken.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-PMC_KIB = {"k_noise_gen": (66653.9, 1034441.6), "k_frame": (359899.8, 1015954.7)}
+PMC_KIB = {"k_noise_gen": (66636.9, 1034323.6), "k_frame": (359965.3, 1009817.7)}
 
 
 def streaming_bytes(d: int, rounds: int, p: float, shots: int) -> float:
