@@ -249,9 +249,14 @@ def bench_serving(rates=(10, 30, 100, 300, 1000)):
     # is kept below half of the 288 GB of HBM.
     srv = serve.Server(pool, hbm_budget_bytes=96 << 30, num_slots=4, max_chunk_shots=1 << 18,
                        max_chunk_bytes=8 << 30)
+    t0 = time.perf_counter()
+    methods = srv.calibrate()              # frame or sparse sampling per large circuit
+    calibrate_s = time.perf_counter() - t0
     srv.serve(workloads.serving_requests(8, rate=1000.0, pool_size=len(pool), seed=999, max_shots=4096))  # warm-up
     out = {"pool": f"rotated surface codes d=3..101 (odd), rounds=d, p log-uniform [1e-4, 1e-2]",
-           "analysis_s": analysis, "rates": {}}
+           "analysis_s": analysis, "calibrate_s": calibrate_s,
+           "methods": {k: {"frame_ms": v[0], "sparse_ms": v[1], "method": v[2]} for k, v in methods.items()},
+           "rates": {}}
     for rate in rates:
         n = 50 if rate <= 10 else 100
         reqs = workloads.serving_requests(n, rate=float(rate), pool_size=len(pool), seed=rate)

@@ -44,12 +44,19 @@ struct ChunkOut {
   uint64_t random_lane = ~0ull;                         // a lane that depends on a random outcome
 };
 
+// Walks the program backwards for lanes [lane0, lane_end), whose outputs
+// read measurements m_lo .. m_hi only: ops after m_hi see all-zero rows and
+// are skipped, and once m_lo is passed the walk stops as soon as every row
+// is zero again (nothing earlier can then reach these outputs).
 void walk_chunk(const Program &P, const std::vector<Exec> &exec, const std::vector<uint64_t> &gen_base,
                 const std::vector<uint32_t> &moff, const std::vector<uint32_t> &mlanes, uint64_t lane0,
-                uint64_t lane_end, ChunkOut &out) {
+                uint64_t lane_end, uint64_t m_lo, uint64_t m_hi, ChunkOut &out) {
   const size_t CW = kChunkWords;
   const size_t n = P.num_qubits;
   std::vector<uint64_t> X(n * CW, 0), Z(n * CW, 0);
+  // live[q] = 0 guarantees all-zero rows for qubit q (1 means "maybe"), so
+  // the many ops away from a chunk's outputs cost a flag test each.
+  std::vector<uint8_t> live(n, 0);
   auto xr = [&](uint32_t q) { return &X[(size_t)q * CW]; };
   auto zr = [&](uint32_t q) { return &Z[(size_t)q * CW]; };
   auto any = [&](const uint64_t *r) -> uint64_t {
@@ -57,18 +64,24 @@ void walk_chunk(const Program &P, const std::vector<Exec> &exec, const std::vect
     return ~0ull;
   };
   auto check_collapse = [&](uint32_t q) {
+    if (!live[q]) return;
     uint64_t l = any(xr(q));
     if (l != ~0ull && out.random_lane == ~0ull) out.random_lane = l;
   };
   auto clear = [&](uint32_t q) {
+    if (!live[q]) return;
     std::fill(xr(q), xr(q) + CW, 0);
     std::fill(zr(q), zr(q) + CW, 0);
+    live[q] = 0;
   };
   auto add_measurement = [&](uint32_t q, uint64_t m) {
     uint64_t *z = zr(q);
     for (uint32_t a = moff[m]; a < moff[m + 1]; a++) {
       uint64_t l = mlanes[a];
-      if (l >= lane0 && l < lane_end) z[(l - lane0) / 64] ^= 1ull << ((l - lane0) % 64);
+      if (l >= lane0 && l < lane_end) {
+        z[(l - lane0) / 64] ^= 1ull << ((l - lane0) % 64);
+        live[q] = 1;
+      }
     }
   };
   auto emit = [&](const uint64_t *r, uint64_t gid) {
@@ -80,7 +93,26 @@ void walk_chunk(const Program &P, const std::vector<Exec> &exec, const std::vect
       }
     }
   };
+  // Refreshes the live flags; true when no row is non-zero.
+  auto all_zero = [&]() {
+    bool none = true;
+    for (size_t q = 0; q < n; q++) {
+      if (!live[q]) continue;
+      const uint64_t *x = xr((uint32_t)q), *z = zr((uint32_t)q);
+      bool nz = false;
+      for (size_t w = 0; w < CW && !nz; w++) nz = (x[w] | z[w]) != 0;
+      live[q] = nz;
+      none &= !nz;
+    }
+    return none;
+  };
+  uint32_t since_check = 0;
   for (size_t i = exec.size(); i-- > 0;) {
+    if (exec[i].meas > m_hi) continue;         // after the last measurement the lanes read
+    if (exec[i].meas <= m_lo && ++since_check >= 8) {
+      since_check = 0;
+      if (all_zero()) break;
+    }
     const DevOp &op = P.ops[exec[i].pc];
     const uint32_t code = op.code & 0xFFFFu;
     const uint32_t *tg = &P.targets[op.toff];
@@ -99,23 +131,29 @@ void walk_chunk(const Program &P, const std::vector<Exec> &exec, const std::vect
         }
         break;
       case OP_SWAP_XZ:
-        for (uint32_t k = 0; k < op.n; k++) std::swap_ranges(xr(tg[k]), xr(tg[k]) + CW, zr(tg[k]));
+        for (uint32_t k = 0; k < op.n; k++)
+          if (live[tg[k]]) std::swap_ranges(xr(tg[k]), xr(tg[k]) + CW, zr(tg[k]));
         break;
       case OP_Z_XOR_X:
         for (uint32_t k = 0; k < op.n; k++) {
+          if (!live[tg[k]]) continue;
           uint64_t *x = xr(tg[k]), *z = zr(tg[k]);
           for (size_t w = 0; w < CW; w++) z[w] ^= x[w];
         }
         break;
       case OP_X_XOR_Z:
         for (uint32_t k = 0; k < op.n; k++) {
+          if (!live[tg[k]]) continue;
           uint64_t *x = xr(tg[k]), *z = zr(tg[k]);
           for (size_t w = 0; w < CW; w++) x[w] ^= z[w];
         }
         break;
       case OP_CX: case OP_CY: case OP_CZ: case OP_SWAP:
         for (uint32_t k = 0; k < op.n; k++) {
-          uint64_t *xa = xr(tg[2 * k]), *za = zr(tg[2 * k]), *xb = xr(tg[2 * k + 1]), *zb = zr(tg[2 * k + 1]);
+          const uint32_t qa = tg[2 * k], qb = tg[2 * k + 1];
+          if (!live[qa] && !live[qb]) continue;
+          live[qa] = live[qb] = 1;
+          uint64_t *xa = xr(qa), *za = zr(qa), *xb = xr(qb), *zb = zr(qb);
           for (size_t w = 0; w < CW; w++) {
             const uint64_t a = xa[w], b = za[w], c = xb[w], d = zb[w];
             switch (code) {
@@ -133,6 +171,7 @@ void walk_chunk(const Program &P, const std::vector<Exec> &exec, const std::vect
         for (uint32_t k = 0; k < op.n; k++)
           for (uint32_t j = 0; j < Q; j++) {
             const uint32_t q = tg[Q * k + j];
+            if (!live[q]) continue;
             const uint64_t gid = base + 2 * (Q * (uint64_t)k + j);
             emit(zr(q), gid);          // X error: lanes with a Z part on q
             emit(xr(q), gid + 1);      // Z error: lanes with an X part on q
@@ -201,10 +240,27 @@ ErrorModel build_error_model(const Program &P) {
   const size_t nchunks = (size_t)((lanes + 64 * kChunkWords - 1) / (64 * kChunkWords));
   std::vector<ChunkOut> outs(nchunks);
   std::atomic<size_t> next{0};
+  // Measurement range read by each chunk's lanes.
+  std::vector<uint64_t> c_lo(nchunks, ~0ull), c_hi(nchunks, 0);
+  auto note = [&](uint64_t lane, uint64_t m) {
+    const size_t ch = (size_t)(lane / (64 * kChunkWords));
+    c_lo[ch] = std::min(c_lo[ch], m);
+    c_hi[ch] = std::max(c_hi[ch], m);
+  };
+  for (uint64_t d = 0; d < D; d++)
+    for (uint32_t a = P.det_offsets[d]; a < P.det_offsets[d + 1]; a++) note(d, P.det_indices[a]);
+  for (uint64_t o = 0; o < L; o++)
+    for (uint32_t a = P.obs_offsets[o]; a < P.obs_offsets[o + 1]; a++) note(D + o, P.obs_indices[a]);
   auto worker = [&]() {
     for (size_t ch; (ch = next.fetch_add(1)) < nchunks;) {
       const uint64_t l0 = (uint64_t)ch * 64 * kChunkWords;
-      walk_chunk(P, exec, em.gen_base, moff, mlanes, l0, std::min<uint64_t>(lanes, l0 + 64 * kChunkWords), outs[ch]);
+      if (c_lo[ch] == ~0ull) {
+        // Lanes that read no measurement are never flipped; the walk still
+        // checks them for dependence on random outcomes (there is none).
+        continue;
+      }
+      walk_chunk(P, exec, em.gen_base, moff, mlanes, l0, std::min<uint64_t>(lanes, l0 + 64 * kChunkWords),
+                 c_lo[ch], c_hi[ch], outs[ch]);
     }
   };
   const size_t nthreads = std::min<size_t>({nchunks, 16, std::max(1u, std::thread::hardware_concurrency())});

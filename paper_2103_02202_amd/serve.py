@@ -20,6 +20,11 @@ as they arrive:
   on the device.  Big chunks (at least ``big_work`` shot-gates) take slot 0
   one at a time: a large circuit's frames fill the GPU and its last-level
   cache on their own, and two of them side by side only slow each other down.
+* Sampling method per circuit: ``Server.calibrate`` times each large pool
+  circuit's detection events through the frame path and through sparse
+  detection sampling (identical results, Sec. 5.6) and keeps the faster.
+  Chunks of a circuit served by sparse sampling launch one per slot; they
+  need no flip record or frame scratch, so their footprint is the outputs.
 * Latency: arrival (the request's scheduled Poisson time) to the completion of
   its last chunk, observed by polling HIP events; p50 / p99 reported beside
   throughput.
@@ -44,14 +49,22 @@ class PoolCircuit:
         self.name = name
         self.c = stim_gpu.Circuit(text)
         self.c.reference()              # host analysis happens once, at pool load
+        self.method = "frame"           # or "sparse" (see Server.calibrate)
 
     def footprint(self, shots: int) -> int:
         W = (shots + 63) // 64
         c = self.c
+        if self.method == "sparse":
+            return 8 * W * (c.num_detectors + max(c.num_observables, 1))
         b = 8 * W * (c.num_detectors + max(c.num_observables, 1) + max(c.num_measurements, 1))
         if c.num_qubits > LDS_FRAME_LIMIT_QUBITS:
             b += 16 * min(W, GLOBAL_FRAME_WORDS) * c.num_qubits
         return b
+
+    def sample(self, seed, offset, shots, det, obs, stream):
+        """Detection events of one chunk by this circuit's method."""
+        fn = stim_gpu.stim_sparse_detector_sample if self.method == "sparse" else stim_gpu.stim_detector_sample
+        fn(self.c.handle, seed, offset, shots, det, obs, stream)
 
 
 def load_pool(texts, names=None, threads: int = 8):
@@ -85,6 +98,44 @@ class Server:
         self.max_group_work = max_group_shot_gates
         self.keep_outputs = keep_outputs
         self.big_work = big_work
+
+    # -- method per circuit ---------------------------------------------------
+    def calibrate(self, shots: int = 1 << 16, min_qubits: int = 1000, gain: float = 1.2):
+        """Times frame and sparse detection sampling of `shots` shots for every
+        pool circuit of at least `min_qubits` qubits and switches it to sparse
+        sampling when that is at least `gain` times faster.  Returns
+        {name: (frame_ms, sparse_ms or None, method)}."""
+        torch = self.torch
+        out = {}
+        for pc in self.pool:
+            c = pc.c
+            if c.num_qubits < min_qubits:
+                continue
+            try:
+                c.error_sets()                     # builds them, or refuses the circuit
+            except stim_gpu.StimError:
+                out[pc.name] = (None, None, pc.method)
+                continue
+            W = (shots + 63) // 64
+            det = torch.empty((c.num_detectors, W), dtype=torch.int64, device="cuda")
+            obs = torch.empty((max(c.num_observables, 1), W), dtype=torch.int64, device="cuda")
+            times = {}
+            for name, fn in (("frame", stim_gpu.stim_detector_sample),
+                             ("sparse", stim_gpu.stim_sparse_detector_sample)):
+                fn(c.handle, 0, 0, shots, det, obs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(2):
+                    fn(c.handle, 0, 0, shots, det, obs)
+                torch.cuda.synchronize()
+                times[name] = (time.perf_counter() - t0) / 2 * 1e3
+            if times["frame"] >= gain * times["sparse"]:
+                pc.method = "sparse"
+            out[pc.name] = (times["frame"], times["sparse"], pc.method)
+        return out
+
+    def _is_big(self, ch):
+        return ch["pc"].method == "frame" and ch["work"] >= self.big_work
 
     # -- chunks -------------------------------------------------------------
     def _chunks(self, req):
@@ -165,8 +216,8 @@ class Server:
             # groups on the other slots, FIFO, bounded in work so that a
             # launch stays short and later arrivals start soon
             while free_slots and pending:
-                bigs = [ch for ch in pending if ch["work"] >= self.big_work]
-                smalls = [ch for ch in pending if ch["work"] < self.big_work]
+                bigs = [ch for ch in pending if self._is_big(ch)]
+                smalls = [ch for ch in pending if not self._is_big(ch)]
                 small_slots = [x for x in free_slots if x != 0]
                 if 0 in free_slots and not bigs:
                     small_slots.append(0)            # no big chunk waiting: slot 0 takes small ones too
@@ -178,15 +229,16 @@ class Server:
                     slot, queue = small_slots[0], smalls
                 else:
                     break
-                big_slot = queue[0]["work"] >= self.big_work
-                if big_slot:
+                big_slot = self._is_big(queue[0])
+                method = queue[0]["pc"].method
+                if big_slot or method == "sparse":         # one chunk per launch
                     limit_n, limit_w = 1, float("inf")
                 else:
                     limit_n, limit_w = self.max_group, self.max_group_work
                 group, gbytes, gwork = [], 0, 0.0
                 while (queue and len(group) < limit_n and used + gbytes + queue[0]["bytes"] <= self.budget
                        and (not group or gwork + queue[0]["work"] <= limit_w)
-                       and (queue[0]["work"] >= self.big_work) == big_slot):
+                       and self._is_big(queue[0]) == big_slot and queue[0]["pc"].method == method):
                     ch = queue.pop(0)
                     group.append(ch)
                     gbytes += ch["bytes"]
@@ -207,7 +259,11 @@ class Server:
                 with torch.cuda.stream(stream):
                     for ch in group:
                         self._alloc(ch)
-                stim_gpu.stim_batch_sample([self._request_dict(ch) for ch in group], stream=stream)
+                if group[0]["pc"].method == "sparse":
+                    ch = group[0]
+                    ch["pc"].sample(ch["req"]["seed"], ch["offset"], ch["shots"], ch["det"], ch["obs"], stream)
+                else:
+                    stim_gpu.stim_batch_sample([self._request_dict(ch) for ch in group], stream=stream)
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 inflight.append((slot, ev, group, gbytes))
@@ -241,8 +297,7 @@ class Server:
             for ch in chs:
                 with torch.cuda.stream(stream):
                     self._alloc(ch)
-                    stim_gpu.stim_detector_sample(ch["pc"].c.handle, r["seed"], ch["offset"], ch["shots"],
-                                                  ch["det"], ch["obs"], stream)
+                    ch["pc"].sample(r["seed"], ch["offset"], ch["shots"], ch["det"], ch["obs"], stream)
                 stream.synchronize()
                 stats["launches"] += 1
                 stats["chunks"] += 1

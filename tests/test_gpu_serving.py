@@ -77,3 +77,41 @@ def test_one_at_a_time_server_same_results(server_mod):
     torch.cuda.synchronize()
     for r1, r2 in zip(sorted(reqs, key=lambda r: r["seed"]), sorted(reqs2, key=lambda r: r["seed"])):
         assert torch.equal(assembled(r1)[0], assembled(r2)[0])
+
+
+def test_sparse_method_chunks_equal_alone(server_mod):
+    """Circuits served by sparse detection sampling (one chunk per launch)
+    mixed with frame-path circuits: every request equals its frame run alone."""
+    print("[case] serving with sparse circuits", flush=True)
+    texts = [wl.surface_code(d, d, p) for d, p in [(3, 1e-3), (7, 2e-4), (9, 1e-3), (13, 1e-4)]]
+    pool = server_mod.load_pool(texts)
+    pool[1].method = "sparse"
+    pool[3].method = "sparse"
+    reqs = wl.serving_requests(80, rate=3000.0, pool_size=len(pool), seed=11, min_shots=64, max_shots=9000)
+    srv = server_mod.Server(pool, hbm_budget_bytes=32 << 20, num_slots=3, max_chunk_shots=2048, keep_outputs=True)
+    stats = srv.serve(reqs)
+    assert stats["requests"] == 80
+    torch.cuda.synchronize()
+    from paper_2103_02202_amd import stim_gpu
+    for r in reqs:
+        det, obs = assembled(r)
+        c = pool[r["circuit"]].c
+        W = (r["shots"] + 63) // 64
+        d1 = torch.empty((c.num_detectors, W), dtype=torch.int64, device="cuda")
+        o1 = torch.empty((max(c.num_observables, 1), W), dtype=torch.int64, device="cuda")
+        stim_gpu.stim_detector_sample(c.handle, r["seed"], 0, r["shots"], d1, o1)
+        torch.cuda.synchronize()
+        assert torch.equal(det, d1), f"request {r['seed']} differs in the mix"
+        assert torch.equal(obs[: c.num_observables], o1[: c.num_observables])
+
+
+def test_calibration_picks_a_method_per_large_circuit(server_mod):
+    print("[case] serving calibration", flush=True)
+    pool = server_mod.load_pool([wl.surface_code(3, 3, 1e-3), wl.surface_code(25, 25, 1e-4),
+                                 wl.surface_code(25, 25, 5e-3, feedback_reset=True)])
+    srv = server_mod.Server(pool, num_slots=2)
+    got = srv.calibrate(shots=4096, min_qubits=1000)
+    assert set(got) == {pool[1].name, pool[2].name}
+    assert got[pool[1].name][2] in ("frame", "sparse") and got[pool[1].name][1] > 0
+    assert got[pool[2].name] == (None, None, "frame")        # feedback: sparse sampling refuses it
+    assert pool[0].method == "frame" and pool[2].method == "frame"
