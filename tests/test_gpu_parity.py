@@ -281,3 +281,17 @@ def test_feedback_reset_surface_d15(sg):
         assert np.array_equal(full[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["meas"])
         assert np.array_equal(det[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["det"])
         assert np.array_equal(obs[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["obs"])
+
+
+def test_feedback_lookback_across_repeat_iterations(sg):
+    """Controls that reach into the previous iteration of a REPEAT block."""
+    announce("feedback across iterations")
+    text = ("M 0 1\nREPEAT 7 {\n  H 0\n  DEPOLARIZE1(0.2) 0 1\n  M 0 1\n  CX rec[-3] 2 rec[-4] 1\n"
+            "  CZ 0 rec[-2]\n  M 2\n  X_ERROR(0.1) 2\n}\nM 0 1 2\n")
+    for tile, placement in [("1", "lds"), ("2", "global")]:
+        import os
+        os.environ["STIM_TILE_WORDS"], os.environ["STIM_FRAME_PLACEMENT"] = tile, placement
+        try:
+            check_meas(sg, text, 3, 3000)
+        finally:
+            del os.environ["STIM_TILE_WORDS"], os.environ["STIM_FRAME_PLACEMENT"]
