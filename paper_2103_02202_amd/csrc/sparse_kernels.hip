@@ -86,27 +86,30 @@ __global__ void __launch_bounds__(kThreads) k_sparse_events(SparseParams p) {
     uint32_t so[5];
 #pragma unroll
     for (int i = 0; i < 5; i++) so[i] = p.set_off[gk + (i <= (int)(2 * Q) ? i : 0)];
+    // The walk collects, per generator (X_a, Z_a, X_b, Z_b), the shots whose
+    // error contains it; each generator's set is then XORed once.
+    uint64_t m[4] = {0, 0, 0, 0};
     noise_walk(K, p.seed, instr, (uint64_t)s_lo + k, p.word0 + ww, thr, inv_log2_keep, e & 0xFF, SparsePhilox(),
-               [&](int pos, uint32_t ch) {
-                 if ((uint64_t)pos >= shots_left) return;   // past the last shot
-                 // Generator bits X_a, Z_a, X_b, Z_b of the error's Pauli.
-                 uint32_t gens;
-                 if (K == 15) gens = ch + 1;
-                 else if (K == 3) gens = (ch <= 1 ? 1u : 0u) | (ch >= 1 ? 2u : 0u);
-                 else gens = code == OP_NOISE_X ? 1u : code == OP_NOISE_Z ? 2u : 3u;
-                 const uint64_t bit = 1ull << pos;
+               [&](int pos, uint32_t ch) { add_error(K, pos, ch, m); });
+    if (shots_left < 64) {                       // past the last shot
 #pragma unroll
-                 for (uint32_t gb = 0; gb < 4; gb++) {
-                   if (gb >= 2 * Q || !((gens >> gb) & 1)) continue;
-                   for (uint32_t a = so[gb]; a < so[gb + 1]; a++) {
-                     const uint32_t l = p.set_lanes[a];
-                     uint64_t *dst = l < p.num_det ? p.det + (uint64_t)l * W + ww
-                                                   : p.obs + (uint64_t)(l - p.num_det) * W + ww;
-                     if (l < p.num_det || p.obs != nullptr)
-                       __hip_atomic_fetch_xor(dst, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                   }
-                 }
-               });
+      for (int g = 0; g < 4; g++) m[g] &= (1ull << shots_left) - 1;
+    }
+    if (K == 0) {                                // one Pauli: X (x), Z (z) or Y (both)
+      const uint64_t v = m[0];
+      m[0] = code != OP_NOISE_Z ? v : 0;
+      m[1] = code != OP_NOISE_X ? v : 0;
+    }
+#pragma unroll
+    for (uint32_t gb = 0; gb < 4; gb++) {
+      if (gb >= 2 * Q || !m[gb]) continue;
+      for (uint32_t a = so[gb]; a < so[gb + 1]; a++) {
+        const uint32_t l = p.set_lanes[a];
+        uint64_t *dst = l < p.num_det ? p.det + (uint64_t)l * W + ww : p.obs + (uint64_t)(l - p.num_det) * W + ww;
+        if (l < p.num_det || p.obs != nullptr)
+          __hip_atomic_fetch_xor(dst, m[gb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
   };
   for (uint64_t b = c_begin + wave * 64; b < c_end; b += kThreads) {
     const uint64_t c = b + lane;
@@ -223,27 +226,38 @@ __global__ void __launch_bounds__(kWindowThreads) k_sparse_window(SparseWindowPa
 #pragma unroll
     for (int a = 0; a < 5; a++) so[a] = p.set_off[gk + (a <= (int)(2 * Q) ? a : 0)];
     const uint64_t shots_left = p.num_shots - 64 * (tw0 + j);
+    uint64_t m[4] = {0, 0, 0, 0};               // shots per generator, as in the global kernel
     noise_walk(K, p.seed, s_instr[i], (uint64_t)s_slo[i] + k, p.word0 + tw0 + j, thr_all + i * 64, s_inv[i],
-               e & 0xFF, SparsePhilox(), [&](int pos, uint32_t ch) {
-                 if ((uint64_t)pos >= shots_left) return;
-                 uint32_t gens;
-                 if (K == 15) gens = ch + 1;
-                 else if (K == 3) gens = (ch <= 1 ? 1u : 0u) | (ch >= 1 ? 2u : 0u);
-                 else gens = code == OP_NOISE_X ? 1u : code == OP_NOISE_Z ? 2u : 3u;
-                 const uint64_t bit = 1ull << pos;
+               e & 0xFF, SparsePhilox(), [&](int pos, uint32_t ch) { add_error(K, pos, ch, m); });
+    if (shots_left < 64) {
 #pragma unroll
-                 for (uint32_t gb = 0; gb < 4; gb++) {
-                   if (gb >= 2 * Q || !((gens >> gb) & 1)) continue;
-                   for (uint32_t a = so[gb]; a < so[gb + 1]; a++) {
-                     const uint32_t l = p.set_lanes[a];
-                     // The batch plan keeps every detector row it touches
-                     // inside the window; the test only guards the LDS.
-                     if (l < D && l - cur_base >= WIN) continue;
-                     uint64_t *dst = l < D ? win + slot_of(l) * T + j : obs_acc + (l - D) * T + j;
-                     __hip_atomic_fetch_xor(dst, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                   }
-                 }
-               });
+      for (int g = 0; g < 4; g++) m[g] &= (1ull << shots_left) - 1;
+    }
+    if (K == 0) {
+      const uint64_t v = m[0];
+      m[0] = code != OP_NOISE_Z ? v : 0;
+      m[1] = code != OP_NOISE_X ? v : 0;
+    }
+    const uint32_t base32 = (uint32_t)cur_base;
+#pragma unroll
+    for (uint32_t gb = 0; gb < 4; gb++) {
+      if (gb >= 2 * Q || !m[gb]) continue;
+      for (uint32_t a = so[gb]; a < so[gb + 1]; a++) {
+        const uint32_t l = p.set_lanes[a];
+        uint64_t *dst;
+        if (l < (uint32_t)D) {
+          // The batch plan keeps every detector row it touches inside the
+          // window; the test only guards the LDS.
+          const uint32_t off = l - base32;
+          if (off >= WIN) continue;
+          const uint32_t sl = off + ring0 >= WIN ? off + ring0 - WIN : off + ring0;
+          dst = win + sl * T + j;
+        } else {
+          dst = obs_acc + (l - (uint32_t)D) * T + j;
+        }
+        __hip_atomic_fetch_xor(dst, m[gb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
   };
 
   __syncthreads();
