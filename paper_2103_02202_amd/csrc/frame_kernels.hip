@@ -131,12 +131,7 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
       j = (int)(c % T);
       if (j < tl.valid) {
         r = philox_call(instr, g, p.word0 + tl.tw0 + j, PURPOSE_NOISE_PREFIX << 32, p.seed);
-#pragma unroll
-        for (uint32_t b = 0; b < 32; b++) {
-          uint32_t s = g * 32 + b;
-          uint64_t vp = (r.v[b >> 3] >> (8 * (b & 7))) & 0xFF;
-          if (s >= s_lo && s < s_hi && vp >= cut) mask |= 1u << b;
-        }
+        mask = prefix_pass_mask(r, cut) & group_slot_mask(g, s_lo, s_hi);
       }
     }
     uint32_t total;
@@ -460,12 +455,7 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
     U64x4 r{{0, 0, 0, 0}};
     if (c < all_cand && tw0 + j < g.num_words) {
       r = philox_call(instr, grp, g.word0 + tw0 + j, PURPOSE_NOISE_PREFIX << 32, g.seed);
-#pragma unroll
-      for (uint32_t b = 0; b < 32; b++) {
-        const uint32_t s = grp * 32 + b;
-        const uint64_t vp = (r.v[b >> 3] >> (8 * (b & 7))) & 0xFF;
-        if (s >= s_lo && s < s_hi && vp >= cut) mask |= 1u << b;
-      }
+      mask = prefix_pass_mask(r, cut) & group_slot_mask(grp, s_lo, s_hi);
     }
     // Queue positions: one LDS atomic per (wave, tile) present in the wave.
     bool pending = mask != 0;

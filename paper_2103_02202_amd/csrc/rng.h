@@ -102,6 +102,39 @@ STIM_HD uint64_t noise_prefix(uint64_t seed, uint64_t instr, uint64_t slot, uint
   return (lane_of(r, k >> 3) >> (8 * (k & 7))) & 0xFF;
 }
 
+// The 8-bit prefixes of one prefix call: bit k of the result is set when
+// prefix k (byte k % 8 of lane k / 8, least significant byte first) is at
+// least `cut` (0..255), i.e. when slot group position k may hold an error.
+// Bytewise unsigned compare without per-byte loops: the low seven bits are
+// compared with the byte's top bit forced on (no borrow leaves the byte),
+// then the top bits decide where they differ.
+STIM_HD uint32_t prefix_pass_mask(const U64x4 &r, uint64_t cut) {
+  const uint64_t H = 0x8080808080808080ull, L = 0x7F7F7F7F7F7F7F7Full;
+  const uint64_t y = cut * 0x0101010101010101ull;
+  const uint64_t yh = y & H, yl = y & L;
+  uint32_t out = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const uint64_t x = r.v[i];
+    const uint64_t xh = x & H;
+    const uint64_t lo_ge = ((x & L) | H) - yl;                // bit 7 of a byte: low 7 bits x >= y
+    const uint64_t ge = ((xh & ~yh) | (~(xh ^ yh) & lo_ge)) & H;
+    // Gather the eight top bits into one byte.
+    out |= (uint32_t)(((ge >> 7) * 0x0102040810204080ull) >> 56) << (8 * i);
+  }
+  return out;
+}
+
+// Bits [lo - 32 g, hi - 32 g) of a 32-slot group g: the group's slots that
+// belong to the slot range [lo, hi).
+STIM_HD uint32_t group_slot_mask(uint32_t g, uint32_t lo, uint32_t hi) {
+  const int64_t a = (int64_t)lo - 32 * (int64_t)g, b = (int64_t)hi - 32 * (int64_t)g;
+  const int64_t a0 = a < 0 ? 0 : a, b0 = b > 32 ? 32 : b;
+  if (b0 <= a0) return 0u;
+  const uint64_t bits = ((1ull << (b0 - a0)) - 1) << a0;
+  return (uint32_t)bits;
+}
+
 // G = #{g in 1..64 : u < t[g-1]} for non-increasing t.
 STIM_HD int gap_length(uint64_t u, const uint64_t *t) {
   int lo = 0, hi = 64;

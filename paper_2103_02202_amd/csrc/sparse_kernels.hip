@@ -120,12 +120,7 @@ __global__ void __launch_bounds__(kThreads) k_sparse_events(SparseParams p) {
       grp = g_lo + (uint32_t)(c / W);
       w = c % W;
       r = philox4x64_10(instr, grp, p.word0 + w, PURPOSE_NOISE_PREFIX << 32, p.seed, KEY_HI);
-#pragma unroll
-      for (uint32_t k = 0; k < 32; k++) {
-        const uint32_t s = grp * 32 + k;
-        const uint64_t vp = (r.v[k >> 3] >> (8 * (k & 7))) & 0xFF;
-        if (s >= s_lo && s < s_hi && vp >= cut) mask |= 1u << k;
-      }
+      mask = prefix_pass_mask(r, cut) & group_slot_mask(grp, s_lo, s_hi);
     }
     uint32_t total;
     const uint32_t first = wave_exclusive_scan((uint32_t)__builtin_popcount(mask), lane, &total);
@@ -306,14 +301,7 @@ __global__ void __launch_bounds__(kWindowThreads) k_sparse_window(SparseWindowPa
         j = (int)(local % T);
         if (j < valid) {
           r = philox4x64_10(s_instr[i], grp, p.word0 + tw0 + j, PURPOSE_NOISE_PREFIX << 32, p.seed, KEY_HI);
-          const uint64_t cut = s_cut[i];
-          const uint32_t lo = s_slo[i], hi = s_shi[i];
-#pragma unroll
-          for (uint32_t k = 0; k < 32; k++) {
-            const uint32_t s = grp * 32 + k;
-            const uint64_t vp = (r.v[k >> 3] >> (8 * (k & 7))) & 0xFF;
-            if (s >= lo && s < hi && vp >= cut) mask |= 1u << k;
-          }
+          mask = prefix_pass_mask(r, s_cut[i]) & group_slot_mask(grp, s_slo[i], s_shi[i]);
         }
       }
       uint32_t total;
