@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE all bytes written.  None when the kernels changed after the
 # counters were taken.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-PMC_KIB = {"k_noise_gen": (66636.9, 1034323.6), "k_frame": (359965.3, 1009817.7)}
+PMC_KIB = {"k_noise_gen": (66028.3, 1025820.0), "k_frame": (359990.9, 1010619.0)}
 
 
 def streaming_bytes(d: int, rounds: int, p: float, shots: int) -> float:
