@@ -96,11 +96,20 @@ int ensure_reference(stim_circuit *c, hipStream_t s = nullptr, bool allow_gpu = 
   if (gpu) {
     std::string err;
     std::vector<uint64_t> bits;
-    const int rc = gpu_reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements, bits, s, err);
-    if (rc) return set_error(rc, err);
-    c->ref = std::move(bits);
-    c->have_ref = true;
-    return STIM_OK;
+    int rc;
+    try {
+      rc = gpu_reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements, bits, s, err);
+    } catch (const std::bad_alloc &) {
+      return set_error(STIM_E_OOM, "out of host memory planning the GPU reference sample");
+    }
+    if (rc == STIM_OK) {
+      c->ref = std::move(bits);
+      c->have_ref = true;
+      return STIM_OK;
+    }
+    // A circuit the GPU planner does not take (too many unrolled steps) is
+    // left to the host tableau, which walks it without unrolling it.
+    if (rc != STIM_E_UNSUPPORTED) return set_error(rc, err);
   }
   try {
     c->ref = reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements);
@@ -180,6 +189,9 @@ int ensure_error_model(stim_circuit *c) {
     } catch (const std::bad_alloc &) {
       c->em_code = STIM_E_OOM;
       c->em_msg = "out of host memory building the error sets";
+    } catch (const std::exception &e) {
+      c->em_code = STIM_E_UNSUPPORTED;
+      c->em_msg = std::string("building the error sets failed: ") + e.what();
     }
   }
   return c->em_code ? set_error(c->em_code, c->em_msg) : STIM_OK;
@@ -1083,8 +1095,13 @@ int stim_reference_sample_gpu(stim_circuit *c, uint64_t *ref_out, void *hip_stre
   std::lock_guard<std::mutex> lock(c->mu);
   std::string err;
   std::vector<uint64_t> bits;
-  const int rc = gpu_reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements, bits,
-                                      (hipStream_t)hip_stream, err);
+  int rc;
+  try {
+    rc = gpu_reference_sample(c->tree, c->prog.num_qubits, c->prog.num_measurements, bits, (hipStream_t)hip_stream,
+                              err);
+  } catch (const std::bad_alloc &) {
+    return set_error(STIM_E_OOM, "out of host memory planning the GPU reference sample");
+  }
   if (rc) return set_error(rc, err);
   if (ref_out && !bits.empty()) std::memcpy(ref_out, bits.data(), bits.size() * sizeof(uint64_t));
   if (!c->have_ref) {

@@ -326,6 +326,7 @@ __global__ void k_ref_zero(uint64_t *p, size_t n) {
 }
 
 // Host-side plan: the unrolled circuit as kernel steps.
+constexpr size_t kMaxSteps = 20000000;
 struct Planner {
   std::vector<Step> steps;
   std::vector<uint32_t> targets;
@@ -370,10 +371,17 @@ struct Planner {
     }
   }
 
+  bool too_long = false;
+
   void walk(const std::vector<Node> &nodes) {
     for (const Node &n : nodes) {
+      if (too_long) return;
+      if (steps.size() > kMaxSteps) {          // e.g. a huge REPEAT count: leave it to the host
+        too_long = true;
+        return;
+      }
       if (n.repeat) {
-        for (uint64_t r = 0; r < n.reps; r++) walk(n.body);
+        for (uint64_t r = 0; r < n.reps && !too_long; r++) walk(n.body);
         continue;
       }
       if (n.gate == G_M || n.gate == G_MR || n.gate == G_R) {
@@ -425,6 +433,10 @@ int gpu_reference_sample(const std::vector<Node> &tree, uint64_t num_qubits, uin
   }
   Planner P(n);
   P.walk(tree);
+  if (P.too_long) {
+    err = "circuit too long for the GPU reference sampler";
+    return STIM_E_UNSUPPORTED;
+  }
   const uint64_t nw = (n + 63) / 64, nwp = transpose_stride(n);          // column stride
   const uint64_t s2 = transpose_stride(2 * n);                           // row stride (transposed)
   Tab t{nullptr, nullptr, nullptr, (uint32_t)n, (uint32_t)nw, (uint32_t)nwp};
