@@ -120,3 +120,15 @@ def test_sparse_falls_back_when_no_window_fits(sg, text):
     torch.cuda.synchronize()
     assert torch.equal(det, fdet) and torch.equal(obs, fobs)
     assert int(torch.count_nonzero(det)) + int(torch.count_nonzero(obs)) > 0
+
+
+def test_sparse_d101_equals_frame(sg):
+    """d=101 (no detector window fits in LDS: the global-atomic kernel) at
+    16,384 shots, against the frame path on the global-frame walk."""
+    announce("sparse d101")
+    c = sg.Circuit(wl.surface_code(101, 101, 1e-3))
+    det, obs = c.detect_sparse(6, 16384)
+    fdet, fobs = c.detect(6, 16384)
+    torch.cuda.synchronize()
+    assert torch.equal(det, fdet) and torch.equal(obs, fobs)
+    assert int(torch.count_nonzero(det)) > 0
