@@ -441,6 +441,35 @@ int cu_count(int dev) {
   return n;
 }
 
+// Noise pre-pass reservations at tile width T over `ntiles` tiles: for each
+// noise execution, mean + 6 sigma + 16 records per tile for the expected
+// number of words whose prefix admits an error (0 = too many for one
+// workgroup's queue: that execution stays inline), and its first record.
+// Returns the total number of records.
+constexpr uint64_t kMaxRecordBytes = 8ull << 30;
+constexpr size_t kMaxGenInstances = 65535;          // noise executions per pre-pass launch (grid rows)
+
+uint64_t noise_reservations(const Program &P, int T, uint64_t ntiles, std::vector<uint32_t> &cap,
+                            std::vector<uint64_t> &base, uint32_t &max_cap) {
+  const size_t ninst = P.noise_pc.size();
+  cap.assign(ninst, 0);
+  base.assign(ninst, 0);
+  max_cap = 1;
+  uint64_t nrec = 0;
+  for (size_t i = 0; i < ninst; i++) {
+    const DevOp &op = P.ops[P.noise_pc[i]];
+    const uint64_t cut = P.thresholds[(size_t)op.aux * 64 + 63] >> 56;
+    const double q = (256.0 - (double)cut) / 256.0;
+    const double mu = (double)op.n * T * q;
+    const double capd = std::ceil(mu + 6.0 * std::sqrt(mu) + 16.0);
+    cap[i] = capd > (double)kGenQueue ? 0u : (uint32_t)capd;
+    max_cap = std::max(max_cap, cap[i]);
+    base[i] = nrec;
+    nrec += (uint64_t)cap[i] * ntiles;
+  }
+  return nrec;
+}
+
 // Runs the frame kernel; ref == nullptr writes raw flips.
 int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
               const uint64_t *ref, uint64_t *out, hipStream_t s) {
@@ -469,28 +498,14 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   const Program &P = c->prog;
   const size_t ninst = P.noise_pc.size();
   const char *pre_env = std::getenv("STIM_NOISE_PREPASS");
-  bool prepass = ninst > 0 && !(pre_env && std::strcmp(pre_env, "0") == 0) && ntiles <= 0x7FFFFFFFull &&
-                 P.num_qubits < (1ull << 27);                    // records hold 27-bit qubit indices
-  // Reservations above this many records per (execution, tile) stay inline.
-  const uint32_t kMaxTileRecords = kGenQueue;
-  std::vector<uint64_t> nbase(ninst);
-  std::vector<uint32_t> ncap(ninst);
+  bool prepass = ninst > 0 && ninst <= kMaxGenInstances && !(pre_env && std::strcmp(pre_env, "0") == 0) &&
+                 ntiles <= 0x7FFFFFFFull && P.num_qubits < (1ull << 27);  // records hold 27-bit qubit indices
+  std::vector<uint64_t> nbase;
+  std::vector<uint32_t> ncap;
   uint64_t nrec = 0;
   uint32_t max_cap = 1;
   if (prepass) {
-    for (size_t i = 0; i < ninst; i++) {
-      const DevOp &op = P.ops[P.noise_pc[i]];
-      const uint64_t cut = P.thresholds[(size_t)op.aux * 64 + 63] >> 56;
-      const double q = (256.0 - (double)cut) / 256.0;
-      const double mu = (double)op.n * cfg.tile_words * q;
-      double capd = std::ceil(mu + 6.0 * std::sqrt(mu) + 16.0);
-      uint32_t cap = capd > (double)kMaxTileRecords ? 0u : (uint32_t)capd;
-      ncap[i] = cap;
-      max_cap = std::max(max_cap, cap);
-      nbase[i] = nrec;
-      nrec += (uint64_t)cap * ntiles;
-    }
-    const uint64_t kMaxRecordBytes = 8ull << 30;
+    nrec = noise_reservations(P, cfg.tile_words, ntiles, ncap, nbase, max_cap);
     if (nrec == 0 || nrec * 16 > kMaxRecordBytes) prepass = false;
   }
   uint2 *d_meta = nullptr;
@@ -553,6 +568,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.word0 = p.word0;
     g.num_words = W;
     g.tiles = (uint32_t)ntiles;
+    g.meta_stride = (uint32_t)ntiles;
     g.meta = d_meta;
     g.rec = d_rec;
     // Each workgroup takes as many tiles of one execution as its LDS queue
@@ -639,7 +655,34 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   double tuned_ms = 0;
+  // Noise pre-pass of each batched noisy request (as in the single-request
+  // path): records and meta entries sized for every candidate tile width,
+  // reservations per width (index log2 of the width: 1, 2, 4, 8).
+  struct Noise {
+    uint2 *meta = nullptr;
+    uint4 *rec = nullptr;
+    uint32_t *cap[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t *base[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t max_cap[4] = {1, 1, 1, 1};
+    uint32_t ninst = 0, stride = 0;
+  };
+  std::vector<Noise> noise;                   // per request; meta == nullptr: noise drawn inline
 };
+
+int width_index(int T) { return T == 1 ? 0 : T == 2 ? 1 : T == 4 ? 2 : 3; }
+
+void free_batch_noise(BatchPlan &pl, hipStream_t s, bool async) {
+  for (BatchPlan::Noise &nz : pl.noise) {
+    std::vector<void *> ptrs = {nz.meta, nz.rec};
+    for (int k = 0; k < 4; k++) {
+      ptrs.push_back(nz.cap[k]);
+      ptrs.push_back(nz.base[k]);
+    }
+    for (void *q : ptrs)
+      if (q) (void)(async ? hipFreeAsync(q, s) : hipFree(q));
+  }
+  pl.noise.clear();
+}
 
 std::mutex g_batch_mu;
 std::vector<std::unique_ptr<BatchPlan>> g_plans;           // most recent last
@@ -651,6 +694,62 @@ void free_plan(BatchPlan *pl) {
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   void *ptrs[] = {pl->d_params, pl->d_items, pl->d_counter, pl->d_flips};
   for (void *q : ptrs) if (q) (void)hipFree(q);
+  free_batch_noise(*pl, nullptr, false);
+}
+
+// Sets up the noise pre-pass of every batched noisy request for the tile
+// widths in `widths` (device memory from the stream-ordered pool when
+// `async`, else plain allocations kept with the plan).  A request whose
+// records would exceed the per-pass limit keeps drawing its noise inline.
+int prepare_batch_noise(BatchPlan &pl, const std::vector<int> &widths, hipStream_t s, bool async) {
+  pl.noise.assign(pl.reqs.size(), BatchPlan::Noise{});
+  const char *pre_env = std::getenv("STIM_NOISE_PREPASS");
+  if (pre_env && std::strcmp(pre_env, "0") == 0) return STIM_OK;
+  auto alloc = [&](void **ptr, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 8);
+    return async ? hipMallocAsync(ptr, bytes, s) : hipMalloc(ptr, bytes);
+  };
+  auto upload = [&](const void *src, size_t bytes, void *dst) -> int {
+    if (async) return stage_upload(src, bytes, dst, s);
+    const hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    return e == hipSuccess ? STIM_OK : hip_error(e, "batch noise upload");
+  };
+  int min_T = 8;
+  for (int T : widths) min_T = std::min(min_T, T);
+  for (size_t i : pl.batched) {
+    const stim_request &r = pl.reqs[i];
+    const Program &P = r.c->prog;
+    const size_t ninst = P.noise_pc.size();
+    if (ninst == 0 || ninst > kMaxGenInstances || P.num_qubits >= (1ull << 27)) continue;
+    const uint64_t W = (r.num_shots + 63) / 64;
+    std::vector<uint32_t> caps[4];
+    std::vector<uint64_t> bases[4];
+    uint32_t max_caps[4] = {1, 1, 1, 1};
+    uint64_t total = 0;
+    for (int T : widths) {
+      const int k = width_index(T);
+      total = std::max(total, noise_reservations(P, T, (W + T - 1) / T, caps[k], bases[k], max_caps[k]));
+    }
+    if (total == 0 || total * 16 > kMaxRecordBytes) continue;
+    BatchPlan::Noise &nz = pl.noise[i];
+    nz.ninst = (uint32_t)ninst;
+    nz.stride = (uint32_t)((W + min_T - 1) / min_T);
+    hipError_t e;
+    if ((e = alloc((void **)&nz.meta, ninst * nz.stride * sizeof(uint2))) != hipSuccess ||
+        (e = alloc((void **)&nz.rec, total * 16)) != hipSuccess)
+      return set_error(STIM_E_OOM, "batch noise record allocation failed");
+    for (int T : widths) {
+      const int k = width_index(T);
+      nz.max_cap[k] = max_caps[k];
+      if ((e = alloc((void **)&nz.cap[k], ninst * sizeof(uint32_t))) != hipSuccess ||
+          (e = alloc((void **)&nz.base[k], ninst * sizeof(uint64_t))) != hipSuccess)
+        return set_error(STIM_E_OOM, "batch noise table allocation failed");
+      int rc = upload(caps[k].data(), ninst * sizeof(uint32_t), nz.cap[k]);
+      if (!rc) rc = upload(bases[k].data(), ninst * sizeof(uint64_t), nz.base[k]);
+      if (rc) return rc;
+    }
+  }
+  return STIM_OK;
 }
 
 void drop_plans_using(const stim_circuit *c) {
@@ -689,6 +788,33 @@ std::string shape_class(const BatchPlan &pl) {
 
 hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
   hipError_t e = hipSuccess;
+  // Noise pre-passes of the noisy requests, at the plan's tile width.
+  const int T = pl.cfg.tile_words, k = width_index(T);
+  for (size_t i : pl.batched) {
+    if (i >= pl.noise.size() || !pl.noise[i].meta) continue;
+    const BatchPlan::Noise &nz = pl.noise[i];
+    const stim_request &r = pl.reqs[i];
+    DeviceCopy &d = r.c->dev[pl.device];
+    const uint64_t W = (r.num_shots + 63) / 64;
+    NoiseGenParams g{};
+    g.ops = d.ops;
+    g.targets = d.targets;
+    g.thresholds = d.thresholds;
+    g.inst_pc = d.noise_pc;
+    g.inst_instr = d.noise_instr;
+    g.base = nz.base[k];
+    g.cap = nz.cap[k];
+    g.seed = r.seed;
+    g.word0 = r.shot_offset / 64;
+    g.num_words = W;
+    g.tiles = (uint32_t)((W + T - 1) / T);
+    g.meta_stride = nz.stride;
+    g.meta = nz.meta;
+    g.rec = nz.rec;
+    g.tiles_per_group = std::max<uint32_t>(1, std::min<uint32_t>(kGenTiles, kGenQueue / nz.max_cap[k]));
+    g.queue_per_tile = kGenQueue / g.tiles_per_group;
+    if ((e = launch_noise_gen(g, T, nz.ninst, 512, s)) != hipSuccess) return e;
+  }
   if (pl.num_items) {
     e = launch_batch(pl.d_params, pl.d_items, pl.num_items, pl.d_counter, pl.cfg, pl.max_n, pl.blocks, s);
     if (e != hipSuccess) return e;
@@ -738,6 +864,12 @@ void batch_params(BatchPlan &pl, std::vector<FrameParams> &params, uint64_t *fli
     } else {
       p.ref = d.ref;
       p.out = r.out0;
+    }
+    if (i < pl.noise.size() && pl.noise[i].meta) {
+      p.noise_meta = pl.noise[i].meta;
+      p.noise_rec = pl.noise[i].rec;
+      p.noise_tiles = pl.noise[i].stride;
+      p.noise_instances = pl.noise[i].ninst;
     }
   }
 }
@@ -804,11 +936,13 @@ int run_one_shot(BatchPlan &pl, hipStream_t s) {
       (e = hipMallocAsync((void **)&pl.d_counter, sizeof(uint32_t), s)) != hipSuccess ||
       (total_flips && (e = hipMallocAsync((void **)&pl.d_flips, total_flips * 8, s)) != hipSuccess))
     return set_error(STIM_E_OOM, "batch allocation failed");
+  int rc = prepare_batch_noise(pl, {pl.cfg.tile_words}, s, true);
   std::vector<FrameParams> params;
   batch_params(pl, params, pl.d_flips);
-  int rc = stage_upload(params.data(), params.size() * sizeof(FrameParams), pl.d_params, s);
+  if (!rc) rc = stage_upload(params.data(), params.size() * sizeof(FrameParams), pl.d_params, s);
   if (!rc) rc = stage_upload(items.data(), items.size() * sizeof(BatchItem), pl.d_items, s);
   if (!rc && (e = enqueue_plan(pl, s)) != hipSuccess) rc = hip_error(e, "batch launch");
+  free_batch_noise(pl, s, true);
   void *ptrs[] = {pl.d_params, pl.d_items, pl.d_counter, pl.d_flips};
   for (void *q : ptrs) if (q) (void)hipFreeAsync(q, s);
   pl.d_params = nullptr;
@@ -828,14 +962,6 @@ int build_plan(BatchPlan &pl, hipStream_t s) {
   if (pl.batched.empty()) return STIM_OK;
   if (total_flips && (e = hipMalloc((void **)&pl.d_flips, total_flips * 8)) != hipSuccess)
     return set_error(STIM_E_OOM, "batch flip scratch allocation failed");
-  std::vector<FrameParams> params;
-  batch_params(pl, params, pl.d_flips);
-  if ((e = hipMalloc((void **)&pl.d_params, params.size() * sizeof(FrameParams))) != hipSuccess ||
-      (e = hipMalloc((void **)&pl.d_counter, sizeof(uint32_t))) != hipSuccess)
-    return set_error(STIM_E_OOM, "batch table allocation failed");
-  if ((e = hipMemcpy(pl.d_params, params.data(), params.size() * sizeof(FrameParams), hipMemcpyHostToDevice)) !=
-      hipSuccess)
-    return hip_error(e, "batch table upload");
 
   // Candidate configurations; the work list depends on the tile width.
   std::vector<FrameConfig> cands;
@@ -848,6 +974,20 @@ int build_plan(BatchPlan &pl, hipStream_t s) {
   auto known = g_tuned.find(cls);
   if (known != g_tuned.end()) cands = {known->second};
   else if (!tune) cands = {untuned_batch_config(pl.max_n)};
+
+  std::vector<int> widths;
+  for (const FrameConfig &cfg : cands)
+    if (std::find(widths.begin(), widths.end(), cfg.tile_words) == widths.end()) widths.push_back(cfg.tile_words);
+  int nrc = prepare_batch_noise(pl, widths, s, false);
+  if (nrc) return nrc;
+  std::vector<FrameParams> params;
+  batch_params(pl, params, pl.d_flips);
+  if ((e = hipMalloc((void **)&pl.d_params, params.size() * sizeof(FrameParams))) != hipSuccess ||
+      (e = hipMalloc((void **)&pl.d_counter, sizeof(uint32_t))) != hipSuccess)
+    return set_error(STIM_E_OOM, "batch table allocation failed");
+  if ((e = hipMemcpy(pl.d_params, params.data(), params.size() * sizeof(FrameParams), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return hip_error(e, "batch table upload");
 
   BatchItem *d_items_by_T[9] = {nullptr};
   auto items_for = [&](int T) -> BatchItem * {

@@ -49,9 +49,10 @@ struct NoiseGenParams {
   const uint32_t *cap;          // [instances] 0: leave to the walker
   uint64_t seed, word0, num_words;
   uint32_t tiles;
+  uint32_t meta_stride;         // meta entries per instance (>= tiles)
   uint32_t tiles_per_group;     // tiles per workgroup (at most kGenTiles)
   uint32_t queue_per_tile;      // LDS queue entries per tile (tiles_per_group * this <= kGenQueue)
-  uint2 *meta;                  // [instances][tiles] {count, first record}
+  uint2 *meta;                  // [instances][meta_stride] {count, first record}
   uint4 *rec;
 };
 

@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   const uint32_t inst = blockIdx.y;
   const uint32_t t0 = blockIdx.x * g.tiles_per_group;
   const uint32_t S = g.tiles - t0 < g.tiles_per_group ? g.tiles - t0 : g.tiles_per_group;
-  uint2 *meta = g.meta + (size_t)inst * g.tiles + t0;
+  uint2 *meta = g.meta + (size_t)inst * g.meta_stride + t0;
   const uint32_t cap = g.cap[inst];
   const uint64_t base = g.base[inst];
   if (cap == 0) {
@@ -809,6 +809,7 @@ hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t in
                             hipStream_t stream) {
   if (instances == 0 || g.tiles == 0) return hipSuccess;
   if (instances > 65535 || threads == 0 || threads % 64 || threads > 512 || g.tiles_per_group == 0 ||
+      g.meta_stride < g.tiles ||
       g.tiles_per_group > kGenTiles || g.queue_per_tile == 0 ||
       (size_t)g.tiles_per_group * g.queue_per_tile > kGenQueue)
     return hipErrorInvalidValue;
