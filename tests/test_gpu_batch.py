@@ -152,3 +152,43 @@ def test_batch_with_feedback_requests(sg):
         o = oracle.Circuit(text)
         want = o.sample(seed, offset, shots, meas=mode == 0, det=mode == 1, obs=mode == 1)
         assert np.array_equal(r["out0"].cpu().numpy().view(np.uint64), want["meas" if mode == 0 else "det"])
+
+
+def test_batch_prepass_equals_inline_noise(sg, monkeypatch):
+    """The per-request noise pre-pass and inline noise draw the same errors:
+    batches with and without it agree bit for bit, on every submission
+    (direct, tuned + captured, replay)."""
+    announce("batch pre-pass vs inline")
+    specs = [s for s in SPECS if "ERROR" in s[0] or "DEPOLARIZE" in s[0]]
+    outs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("STIM_NOISE_PREPASS", flag)
+        reqs, circs = make_requests(sg, specs)
+        got = []
+        for _ in range(3):
+            for r in reqs:
+                r["out0"].fill_(-1)
+            sg.stim_batch_sample(reqs)
+            torch.cuda.synchronize()
+            got.append([r["out0"].clone() for r in reqs])
+        for g in got[1:]:
+            assert all(torch.equal(a, b) for a, b in zip(got[0], g))
+        outs[flag] = got[0]
+    for a, b, s in zip(outs["1"], outs["0"], specs):
+        assert torch.equal(a, b), f"request seed {s[2]} differs between pre-pass and inline noise"
+
+
+def test_many_noise_executions_fall_back_to_inline(sg):
+    """More noise executions than one pre-pass launch covers: sampled with
+    inline noise, still equal to the oracle (single and batched)."""
+    text = "REPEAT 70000 {\nX_ERROR(0.002) 0\nCX 0 1\n}\nM 0 1\n"
+    announce("70000 noise executions")
+    specs = [(text, 1000, 21, 0, 0), (wl.surface_code(3, 3, 1e-2), 700, 22, 0, 0)]
+    reqs, circs = make_requests(sg, specs)
+    sg.stim_batch_sample(reqs)
+    torch.cuda.synchronize()
+    o = oracle.Circuit(text)
+    want = o.sample(21, 0, 1000, meas=True)["meas"]
+    assert np.array_equal(reqs[0]["out0"].cpu().numpy().view(np.uint64), want)
+    assert want.any()
+    check_against_single(sg, reqs, circs)
