@@ -141,6 +141,17 @@ int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_of
 int stim_error_sets(stim_circuit *c, uint64_t *num_sets, uint64_t *num_entries, uint32_t *offsets,
                     uint32_t *lanes);
 
+/* Device memory, in bytes, that one sampling call of num_shots shots takes
+ * from the stream-ordered pool of the current device beyond the caller's
+ * outputs, for admission control.  mode 0: stim_frame_sample (noise records
+ * of the pre-pass and their tables; the per-workgroup frame slots of circuits
+ * too large for LDS); mode 1: stim_detector_sample (the same plus the flip
+ * table, one ceil(num_shots / 64)-word row per measurement); mode 2:
+ * stim_sparse_detector_sample (0: it allocates nothing per call).  Host only;
+ * *bytes (host) receives the size.  STIM_E_INVALID_ARG for a null argument or
+ * another mode. */
+int stim_sample_scratch_bytes(stim_circuit *c, uint64_t num_shots, int mode, uint64_t *bytes);
+
 /* One request of a batched launch. mode 0: out0 = measurement record
  * (as stim_frame_sample); mode 1: out0 = detection events, out1 = observable
  * flips or NULL (as stim_detector_sample). */

@@ -470,6 +470,43 @@ uint64_t noise_reservations(const Program &P, int T, uint64_t ntiles, std::vecto
   return nrec;
 }
 
+// Whether a pass over `ntiles` tiles precomputes its noise (records hold
+// 27-bit qubit indices; one pre-pass launch covers 65,535 noise executions).
+bool prepass_enabled(const Program &P, uint64_t ntiles) {
+  const size_t ninst = P.noise_pc.size();
+  const char *pre_env = std::getenv("STIM_NOISE_PREPASS");
+  return ninst > 0 && ninst <= kMaxGenInstances && !(pre_env && std::strcmp(pre_env, "0") == 0) &&
+         ntiles <= 0x7FFFFFFFull && P.num_qubits < (1ull << 27);
+}
+
+// Workgroups in flight (each with its own scratch slot) for a frame kept in
+// global memory: about one per CU, so that the frames stay in the caches.
+uint64_t global_frame_slots(int dev, uint64_t ntiles) {
+  uint64_t slots = (uint64_t)cu_count(dev);
+  if (const char *v = std::getenv("STIM_FRAME_SLOTS")) slots = std::max<long>(1, atol(v));
+  return std::min<uint64_t>(slots, ntiles);
+}
+
+// Device scratch one sampling pass of num_shots allocates: noise records and
+// their tables, and the global frame slots of circuits too large for LDS.
+uint64_t pass_scratch_bytes(const Program &P, uint64_t num_shots, int dev) {
+  const uint64_t W = (num_shots + 63) / 64;
+  const FrameConfig cfg = choose_config(P.num_qubits, W);
+  const uint64_t ntiles = (W + cfg.tile_words - 1) / cfg.tile_words;
+  uint64_t bytes = 0;
+  if (prepass_enabled(P, ntiles)) {
+    std::vector<uint32_t> cap;
+    std::vector<uint64_t> base;
+    uint32_t max_cap = 1;
+    const uint64_t nrec = noise_reservations(P, cfg.tile_words, ntiles, cap, base, max_cap);
+    const uint64_t ninst = P.noise_pc.size();
+    if (nrec > 0 && nrec * 16 <= kMaxRecordBytes) bytes += ninst * ntiles * sizeof(uint2) + ninst * 12 + nrec * 16;
+  }
+  if (!cfg.in_lds)
+    bytes += global_frame_slots(dev, ntiles) * cfg.tile_words * 16 * std::max<uint64_t>(P.num_qubits, 1);
+  return bytes;
+}
+
 // Runs the frame kernel; ref == nullptr writes raw flips.
 int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
               const uint64_t *ref, uint64_t *out, hipStream_t s) {
@@ -497,9 +534,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   // whose reservation would exceed one workgroup's queue stay inline.
   const Program &P = c->prog;
   const size_t ninst = P.noise_pc.size();
-  const char *pre_env = std::getenv("STIM_NOISE_PREPASS");
-  bool prepass = ninst > 0 && ninst <= kMaxGenInstances && !(pre_env && std::strcmp(pre_env, "0") == 0) &&
-                 ntiles <= 0x7FFFFFFFull && P.num_qubits < (1ull << 27);  // records hold 27-bit qubit indices
+  bool prepass = prepass_enabled(P, ntiles);
   std::vector<uint64_t> nbase;
   std::vector<uint32_t> ncap;
   uint64_t nrec = 0;
@@ -598,9 +633,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     // that the frames in flight stay within the last-level cache.
     int dev = 0;
     (void)hipGetDevice(&dev);
-    uint64_t slots = (uint64_t)cu_count(dev);
-    if (const char *v = std::getenv("STIM_FRAME_SLOTS")) slots = std::max<long>(1, atol(v));
-    cfg.slots = (uint32_t)std::min<uint64_t>(slots, ntiles);
+    cfg.slots = (uint32_t)global_frame_slots(dev, ntiles);
     const uint64_t tiles = cfg.slots;
     size_t bytes = (size_t)tiles * cfg.tile_words * 16 * std::max<uint64_t>(c->prog.num_qubits, 1);
     if ((e = hipMallocAsync((void **)&p.scratch, bytes, s)) != hipSuccess) {
@@ -1262,6 +1295,20 @@ int stim_error_sets(stim_circuit *c, uint64_t *num_sets, uint64_t *num_entries, 
   if (offsets) std::memcpy(offsets, c->em.set_off.data(), c->em.set_off.size() * sizeof(uint32_t));
   if (lanes && !c->em.set_lanes.empty())
     std::memcpy(lanes, c->em.set_lanes.data(), c->em.set_lanes.size() * sizeof(uint32_t));
+  return STIM_OK;
+}
+
+int stim_sample_scratch_bytes(stim_circuit *c, uint64_t num_shots, int mode, uint64_t *bytes) {
+  if (!c || !bytes) return set_error(STIM_E_INVALID_ARG, "null argument");
+  if (mode < 0 || mode > 2) return set_error(STIM_E_INVALID_ARG, "mode must be 0, 1 or 2");
+  *bytes = 0;
+  if (num_shots == 0 || mode == 2) return STIM_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const Program &P = c->prog;
+  uint64_t b = pass_scratch_bytes(P, num_shots, dev);
+  if (mode == 1) b += std::max<uint64_t>(P.num_measurements, 1) * ((num_shots + 63) / 64) * sizeof(uint64_t);
+  *bytes = b;
   return STIM_OK;
 }
 

@@ -5,8 +5,9 @@ reference samples uploaded once) and serves detection-event sampling requests
 as they arrive:
 
 * Admission by HBM footprint: a request's device memory -- its detection-event
-  and observable outputs plus the flip record the sampler writes internally
-  (and the frame scratch when the frame is too large for LDS) -- is reserved
+  and observable outputs plus the scratch the library reports for the call
+  (flip record, noise records of the pre-pass, and the frame scratch when the
+  frame is too large for LDS) -- is reserved
   against a byte budget; requests that do not fit wait (a deferral) until
   earlier work completes and releases memory.
 * Chunking: a request is split along the shot axis into chunks of at most
@@ -40,9 +41,6 @@ from concurrent.futures import ThreadPoolExecutor
 
 from . import stim_gpu
 
-LDS_FRAME_LIMIT_QUBITS = 9600       # beyond this the frame slice lives in a global scratch buffer
-GLOBAL_FRAME_WORDS = 256 * 8         # at most this many words of global frame in flight (workgroups x tile words)
-
 
 class PoolCircuit:
     def __init__(self, text: str, name: str):
@@ -52,14 +50,12 @@ class PoolCircuit:
         self.method = "frame"           # or "sparse" (see Server.calibrate)
 
     def footprint(self, shots: int) -> int:
+        """HBM one chunk holds while in flight: its outputs plus the scratch
+        the library takes for it (flip table, noise records, global frame)."""
         W = (shots + 63) // 64
         c = self.c
-        if self.method == "sparse":
-            return 8 * W * (c.num_detectors + max(c.num_observables, 1))
-        b = 8 * W * (c.num_detectors + max(c.num_observables, 1) + max(c.num_measurements, 1))
-        if c.num_qubits > LDS_FRAME_LIMIT_QUBITS:
-            b += 16 * min(W, GLOBAL_FRAME_WORDS) * c.num_qubits
-        return b
+        out = 8 * W * (c.num_detectors + max(c.num_observables, 1))
+        return out + c.scratch_bytes(shots, "sparse" if self.method == "sparse" else "detector")
 
     def sample(self, seed, offset, shots, det, obs, stream):
         """Detection events of one chunk by this circuit's method."""
@@ -140,8 +136,9 @@ class Server:
     # -- chunks -------------------------------------------------------------
     def _chunks(self, req):
         pc = self.pool[req["circuit"]]
-        per_word = max(pc.footprint(64), 1)
-        cap = max(64, min(self.max_chunk, (self.max_chunk_bytes // per_word) * 64))
+        words = (self.max_chunk + 63) // 64
+        per_word = max(pc.footprint(words * 64) / words, 1.0)
+        cap = max(64, min(self.max_chunk, int(self.max_chunk_bytes // per_word) * 64))
         out = []
         off = 0
         while off < req["shots"]:

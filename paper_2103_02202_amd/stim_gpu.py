@@ -49,6 +49,7 @@ def lib():
         L.stim_sparse_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.stim_reference_sample_gpu.argtypes = [vp, vp, vp]
         L.stim_error_sets.argtypes = [vp, P64, P64, vp, vp]
+        L.stim_sample_scratch_bytes.argtypes = [vp, u64, ctypes.c_int, P64]
         L.stim_batch_sample.argtypes = [ctypes.POINTER(StimRequest), ctypes.c_size_t, vp]
         L.stim_format_shots.argtypes = [vp, u64, u64, ctypes.c_int, vp, u64, P64, vp]
         L.stim_kernel_timing.argtypes = [ctypes.c_int]
@@ -136,6 +137,18 @@ def stim_error_sets(handle: int):
     _check(lib().stim_error_sets(h, ctypes.byref(n_sets), ctypes.byref(n_ent), ctypes.c_void_p(off.ctypes.data),
                                  ctypes.c_void_p(lanes.ctypes.data)))
     return off, lanes[: n_ent.value]
+
+
+SCRATCH_MODES = {"frame": 0, "detector": 1, "sparse": 2}
+
+
+def stim_sample_scratch_bytes(handle: int, num_shots: int, mode) -> int:
+    """Device scratch one sampling call takes beyond its outputs (mode
+    'frame', 'detector' or 'sparse', or 0 / 1 / 2)."""
+    m = SCRATCH_MODES[mode] if isinstance(mode, str) else int(mode)
+    b = ctypes.c_uint64()
+    _check(lib().stim_sample_scratch_bytes(ctypes.c_void_p(handle), num_shots, m, ctypes.byref(b)))
+    return int(b.value)
 
 
 def stim_batch_sample(requests, stream=None):
@@ -240,6 +253,9 @@ class Circuit:
 
     def error_sets(self):
         return stim_error_sets(self.handle)
+
+    def scratch_bytes(self, num_shots: int, mode="detector") -> int:
+        return stim_sample_scratch_bytes(self.handle, num_shots, mode)
 
     def reference_gpu(self, stream=None):
         """Canonical reference sample computed on the GPU (uint64 words)."""

@@ -135,3 +135,37 @@ def test_sampling_argument_errors_need_no_gpu():
     assert L.stim_frame_sample(None, 0, 0, 64, ctypes.c_void_p(1), None) == sg.STIM_E_INVALID_ARG
     assert L.stim_detector_sample(h, 0, 65, 64, None, None, None) == sg.STIM_E_INVALID_ARG
     assert L.stim_batch_sample(None, 1, None) == sg.STIM_E_INVALID_ARG
+
+
+def test_sample_scratch_bytes(monkeypatch):
+    """stim_sample_scratch_bytes: detector mode adds one flip row per
+    measurement, sparse sampling allocates nothing per call, a noiseless
+    circuit whose frame fits in LDS needs no scratch, and the noise records of
+    one X_ERROR execution lie between the expected number of 64-shot words an
+    error lands in and its reservation bound (at fewer than 512 words a tile
+    is one word)."""
+    monkeypatch.delenv("STIM_NOISE_PREPASS", raising=False)
+    shots = 64 * 1000
+    W = shots // 64
+    noiseless = sg.Circuit("H 0\nCX 0 1\nM 0 1\n")
+    assert noiseless.scratch_bytes(shots, "frame") == 0
+    assert noiseless.scratch_bytes(shots, "detector") == 8 * W * 2
+    p, n = 0.01, 4
+    c = sg.Circuit(f"X_ERROR({p}) 0 1 2 3\nM 0 1 2 3\nDETECTOR rec[-1]\n")
+    f, d, s = (c.scratch_bytes(shots, m) for m in ("frame", "detector", "sparse"))
+    assert s == 0 and d - f == 8 * W * 4
+    hit = 1 - (1 - p) ** 64
+    lo = 16 * n * hit * W
+    mu_hi = n * min(1.0, hit + 2 / 256)
+    hi = 16 * W * (mu_hi + 6 * mu_hi ** 0.5 + 17) + 8 * W + 12
+    assert lo <= f <= hi, (lo, f, hi)
+    # More noise, more records; at the same tile width, twice the tiles take
+    # twice the records and meta entries (plus the per-execution tables).
+    assert sg.Circuit(f"X_ERROR(0.05) 0 1 2 3\nM 0 1 2 3\n").scratch_bytes(shots, "frame") > f
+    assert c.scratch_bytes(64 * 400, "frame") - 12 == 2 * (c.scratch_bytes(64 * 200, "frame") - 12)
+    # Wider tiles past 1,024 words: fewer records per word.
+    assert c.scratch_bytes(2 * shots, "frame") < 2 * f
+    monkeypatch.setenv("STIM_NOISE_PREPASS", "0")
+    assert c.scratch_bytes(shots, "frame") == 0
+    with pytest.raises(sg.StimError):
+        sg.stim_sample_scratch_bytes(c.handle, shots, 3)
