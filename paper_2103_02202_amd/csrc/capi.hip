@@ -963,13 +963,14 @@ int run_one_shot(BatchPlan &pl, hipStream_t s) {
   pl.num_items = (uint32_t)items.size();
   pl.blocks = (uint32_t)(cu_count(pl.device) * batch_blocks_per_cu(pl.cfg, pl.max_n));
   hipError_t e;
+  int rc = STIM_OK;
   if ((e = hipMallocAsync((void **)&pl.d_params, pl.reqs.size() * sizeof(FrameParams), s)) != hipSuccess ||
       (e = hipMallocAsync((void **)&pl.d_items, std::max<size_t>(items.size(), 1) * sizeof(BatchItem), s)) !=
           hipSuccess ||
       (e = hipMallocAsync((void **)&pl.d_counter, sizeof(uint32_t), s)) != hipSuccess ||
       (total_flips && (e = hipMallocAsync((void **)&pl.d_flips, total_flips * 8, s)) != hipSuccess))
-    return set_error(STIM_E_OOM, "batch allocation failed");
-  int rc = prepare_batch_noise(pl, {pl.cfg.tile_words}, s, true);
+    rc = set_error(STIM_E_OOM, "batch allocation failed");
+  if (!rc) rc = prepare_batch_noise(pl, {pl.cfg.tile_words}, s, true);
   std::vector<FrameParams> params;
   batch_params(pl, params, pl.d_flips);
   if (!rc) rc = stage_upload(params.data(), params.size() * sizeof(FrameParams), pl.d_params, s);
