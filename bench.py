@@ -13,6 +13,8 @@ Prints one JSON line.  Fields beyond the driver's contract:
   cpu_baseline  -- the oracle timed on this host on a bounded shot sample
   analysis_s    -- host compile + reference-sample time
   meas_mode     -- measurement-record sampling (stim_frame_sample) rate
+  host_copy     -- copying one step's events to pinned host memory, and the
+                   PCIe-inclusive rate (outputs otherwise stay in HBM)
   formats       -- shot-major output formats (01, b8, hits, r8) of the run's
                    detection events and record: time and bytes per second
   feedback      -- the same workload with ancillas reset by classically
@@ -85,6 +87,32 @@ def cpu_baseline(text: str, num_gate_targets: int, budget_s: float = 12.0, threa
             "kind": "oracle",
             "sample": f"d={D} surface code, shots [0, {shots}) of the {SHOTS}-shot run, detector mode, "
                       f"{dt:.2f} s sampling; reference sample {ref_s:.2f} s single-threaded"}
+
+
+def bench_host_copy(det, obs, stream, ms_per_step, G):
+    """The step's outputs stay in HBM (`value` has no PCIe part).  For a
+    caller that wants them on the host: the time to copy one step's detection
+    events and observables into pinned host memory, and the PCIe-inclusive
+    rate of step + copy (not overlapped)."""
+    import torch
+    h_det = torch.empty(det.shape, dtype=det.dtype, pin_memory=True)
+    h_obs = torch.empty(obs.shape, dtype=obs.dtype, pin_memory=True)
+    for _ in range(2):
+        h_det.copy_(det, non_blocking=True)
+        h_obs.copy_(obs, non_blocking=True)
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        h_det.copy_(det, non_blocking=True)
+        h_obs.copy_(obs, non_blocking=True)
+    e1.record(stream)
+    e1.synchronize()
+    copy_ms = e0.elapsed_time(e1) / reps
+    nbytes = det.numel() * 8 + obs.numel() * 8
+    return {"bytes": nbytes, "d2h_ms": copy_ms, "d2h_GBps": nbytes / (copy_ms * 1e-3) / 1e9,
+            "pcie_inclusive_shot_gates_per_s": G * SHOTS / ((ms_per_step + copy_ms) * 1e-3)}
 
 
 def bench_batch(steps: int):
@@ -418,6 +446,7 @@ def main():
         "meas_mode": {"ms": pass_ms, "shot_gates_per_s": G * SHOTS / (pass_ms * 1e-3)},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
+    out["host_copy"] = bench_host_copy(det, obs, stream, ms_per_step, G)
     if not args.no_formats:
         out["formats"] = bench_formats(det, meas, Dn, M, SHOTS)
     if not args.no_feedback:
