@@ -531,6 +531,35 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   }
 }
 
+// One program entry, read through the constant address space: the kernel
+// never writes the program, so these uniform loads become scalar loads.  A
+// vector load would first wait (the vector memory counter completes in issue
+// order) for every store and record prefetch still in flight.
+__device__ __forceinline__ DevOp load_op(const DevOp *ops, uint32_t pc) {
+  typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+  ConstU32 *w = (ConstU32 *)(ops + pc);
+  DevOp op;
+  op.code = w[0];
+  op.lead = w[1];
+  op.n = w[2];
+  op.toff = w[3];
+  op.slot0 = w[4];
+  op.aux = w[5];
+  op.aux2 = w[6];
+  op.pad = w[7];
+  return op;
+}
+
+// {count, first record} of a noise execution that has no records.
+__device__ const uint32_t kNoMeta[2] = {kNoRecords, 0u};
+
+// A meta entry, read as uniform scalar loads (the walk never writes it).
+__device__ __forceinline__ uint2 load_meta(const uint32_t *w) {
+  typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+  ConstU32 *c = (ConstU32 *)w;
+  return make_uint2(c[0], c[1]);
+}
+
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
 // LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
 template <int T, bool IN_LDS>
@@ -557,19 +586,20 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   int depth = 0;
   uint32_t noise_seq = 0;
   // Two-stage prefetch of the next noise execution's records.  Stage A (at a
-  // noise op) loads the next execution's {count, first record}; stage B (in
-  // each following op, right after that op's own loads) loads this thread's
-  // first two records.  Both are vector loads issued on every path: scalar
-  // loads would share their wait counter with LDS traffic, and a load issued
-  // on one path only makes later waits conservative.
+  // noise op) loads the next execution's {count, first record}: the same for
+  // the whole workgroup, and never written by the walk, so a scalar load
+  // through the constant address space (it then does not wait behind the
+  // vector loads and stores in flight).  Stage B (in each following op, right
+  // after that op's own loads) loads this thread's first two records with
+  // vector loads issued on every path: a load issued on one path only makes
+  // later waits conservative.
   const bool recs = p.noise_meta != nullptr;
   uint32_t a_inst = 0;
   uint2 a_meta = make_uint2(kNoRecords, 0u);
   auto stage_a = [&](uint32_t inst) {
     const bool ok = recs && inst < p.noise_instances;
-    const uint2 *src = p.noise_meta + (ok ? (size_t)inst * p.noise_tiles + tile : 0);
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(buffer_rsrc(src, ok ? 8u : 0u), 0, 0, 0);
-    a_meta = make_uint2(v[0], v[1]);
+    const uint32_t *src = ok ? (const uint32_t *)(p.noise_meta + (size_t)inst * p.noise_tiles + tile) : kNoMeta;
+    a_meta = load_meta(src);
     a_inst = ok ? inst : 0xFFFFFFFFu;
   };
   uint32_t pf_inst = 0xFFFFFFFFu, pf_count = kNoRecords;
@@ -590,7 +620,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   };
   stage_a(0);
   for (uint32_t pc = 0; pc < p.num_ops; pc++) {
-    const DevOp op = p.ops[pc];
+    const DevOp op = load_op(p.ops, pc);
     const uint32_t code = op.code & 0xFFFFu;
 
     if (code == OP_LOOP_BEGIN) {
