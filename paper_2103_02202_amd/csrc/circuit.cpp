@@ -563,12 +563,18 @@ Program compile_program(const std::vector<Node> &tree) {
     }
     if (!ok) { P.noise_pc.clear(); P.noise_instr.clear(); }
   }
-  // Mark dead Z randomisations on init and collapse targets.
-  for (const DevOp &op : L.prog.ops) {
+  // Mark dead Z randomisations on init and collapse targets, and flag the
+  // collapse ops whose every randomisation is live.
+  for (DevOp &op : L.prog.ops) {
     uint32_t code = op.code & 0xFFFF;
     if (code != OP_INIT && code != OP_R && code != OP_M && code != OP_MR) continue;
+    bool all_live = true;
     for (uint32_t k = 0; k < op.n; k++)
-      if (!w.site_live[op.toff + k]) L.prog.targets[op.toff + k] |= TGT_DEAD_ZRAND;
+      if (!w.site_live[op.toff + k]) {
+        L.prog.targets[op.toff + k] |= TGT_DEAD_ZRAND;
+        all_live = false;
+      }
+    if (all_live) op.code |= OPF_ZRAND_LIVE;
   }
   return L.prog;
 }

@@ -61,6 +61,9 @@ enum OpCode : uint32_t {
 // Flag in OpCode word: this op starts a new instruction (advance the flat
 // index) rather than continuing the previous one after a split.
 constexpr uint32_t OPF_NEW_INSTR = 1u << 16;
+// Flag in OpCode word of a collapse op (INIT, R, M, MR): every target's ZRAND
+// is read later, so the draws need not wait for the target list.
+constexpr uint32_t OPF_ZRAND_LIVE = 1u << 17;
 // Flag on a target word: the ZRAND of this collapse target is never read
 // before it is overwritten, so it need not be drawn.
 constexpr uint32_t TGT_DEAD_ZRAND = 1u << 31;

@@ -193,6 +193,7 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
   const uint32_t *tg = p.targets + op.toff;
   const bool measures = code == OP_M || code == OP_MR;
   const bool use_ref = measures && p.ref != nullptr;
+  const bool all_live = (op.code & OPF_ZRAND_LIVE) != 0;       // uniform
   const uint32_t stride = blockDim.x;
   uint32_t base = threadIdx.x;
   do {
@@ -228,11 +229,17 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
       const uint32_t g = g_lo + c / T;
       const int j = (int)(c % T);
       const uint64_t word = p.word0 + tl.tw0 + j;
-      bool need = false;
-#pragma unroll
-      for (uint32_t u = 0; u < 4; u++) need |= !(tv[v][u] & TGT_DEAD_ZRAND);
       U64x4 r{{0, 0, 0, 0}};
-      if (need) r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+      if (all_live) {
+        // No dependence on the targets: the draw overlaps their loads (and
+        // the stores of the previous op, which complete before them).
+        r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+      } else {
+        bool need = false;
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) need |= !(tv[v][u] & TGT_DEAD_ZRAND);
+        if (need) r = philox_call(instr, g, word, PURPOSE_ZRAND << 32, p.seed);
+      }
       const uint64_t m0 = meas + ((g * 4 > s_lo ? g * 4 : s_lo) - s_lo);
 #pragma unroll
       for (uint32_t u = 0; u < 4; u++) {
