@@ -383,16 +383,22 @@ __device__ __forceinline__ void apply_record(const Tile<T, IN_LDS> &tl, uint32_t
     const int nh = (int)(h & 7);
     for (int i = 0; i < nh; i++)
       add_error(K, (int)((h >> (3 + 11 * i)) & 63), (uint32_t)((h >> (9 + 11 * i)) & 15), mk);
+    // In LDS the XORs are atomics without return: no read-wait-write round
+    // trip.
+    auto flip = [&](uint64_t *w, uint64_t m) {
+      if constexpr (IN_LDS) __hip_atomic_fetch_xor(w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else *w ^= m;
+    };
     if (code == OP_NOISE_DEP2) {
-      tl.FX[tl.at(qa, j)] ^= mk[0];
-      tl.FZ[tl.at(qa, j)] ^= mk[1];
-      tl.FX[tl.at(qb, j)] ^= mk[2];
-      tl.FZ[tl.at(qb, j)] ^= mk[3];
+      flip(tl.FX + tl.at(qa, j), mk[0]);
+      flip(tl.FZ + tl.at(qa, j), mk[1]);
+      flip(tl.FX + tl.at(qb, j), mk[2]);
+      flip(tl.FZ + tl.at(qb, j), mk[3]);
     } else {
       const uint64_t mx = code == OP_NOISE_DEP1 ? mk[0] : code != OP_NOISE_Z ? mk[0] : 0;
       const uint64_t mz = code == OP_NOISE_DEP1 ? mk[1] : code != OP_NOISE_X ? mk[0] : 0;
-      tl.FX[tl.at(qa, j)] ^= mx;
-      tl.FZ[tl.at(qa, j)] ^= mz;
+      flip(tl.FX + tl.at(qa, j), mx);
+      flip(tl.FZ + tl.at(qa, j), mz);
     }
   }
 }
