@@ -716,11 +716,31 @@ __global__ void __launch_bounds__(1024) k_batch(const FrameParams *__restrict__ 
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
     tile_barrier<true>();
-    const uint32_t it = s_item;
+    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
     tile_barrier<true>();
     if (it >= num_items) break;                  // uniform: every wave leaves together
-    const BatchItem bi = items[it];
-    const FrameParams p = reqs[bi.req];
+    // The item and its request's parameters are uniform and never written
+    // by the kernel: scalar loads through the constant address space keep
+    // them in scalar registers (so the walk's own loads through them are
+    // scalar too).
+    typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+    static_assert(sizeof(BatchItem) % 4 == 0 && sizeof(FrameParams) % 4 == 0, "word copies");
+    BatchItem bi;
+    {
+      ConstU32 *src = (ConstU32 *)(items + it);
+      uint32_t w[sizeof(BatchItem) / 4];
+#pragma unroll
+      for (size_t k = 0; k < sizeof(BatchItem) / 4; k++) w[k] = src[k];
+      __builtin_memcpy(&bi, w, sizeof bi);
+    }
+    FrameParams p;
+    {
+      ConstU32 *src = (ConstU32 *)(reqs + bi.req);
+      uint32_t w[sizeof(FrameParams) / 4];
+#pragma unroll
+      for (size_t k = 0; k < sizeof(FrameParams) / 4; k++) w[k] = src[k];
+      __builtin_memcpy(&p, w, sizeof p);
+    }
     walk_tile<T, true>(p, bi.tile, 0, lds);
   }
 }
