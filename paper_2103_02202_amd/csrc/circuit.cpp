@@ -192,6 +192,7 @@ struct Lowering {
   uint32_t pending_lead = 0;
   std::map<uint64_t, uint32_t> threshold_rows;          // bits of p -> row
   std::unordered_map<const Node *, std::vector<uint32_t>> slot_targets;  // collapse slots -> target index
+  std::unordered_map<const Node *, std::vector<uint32_t>> fb_targets;    // controlled pairs -> qubit word index
   uint32_t depth = 0;
 
   uint32_t threshold_row(double p) {
@@ -235,6 +236,8 @@ struct Lowering {
     const OpCode quantum = opcode(n.gate);
     const OpCode fb = n.gate == G_CX ? OP_FB_X : n.gate == G_CY ? OP_FB_Y : OP_FB_Z;
     const size_t pairs = n.targets.size() / 2;
+    std::vector<uint32_t> &fbt = fb_targets[&n];
+    fbt.assign(pairs, 0xFFFFFFFFu);
     std::unordered_map<uint32_t, int> used;
     bool first = true;
     size_t s = 0;
@@ -253,6 +256,7 @@ struct Lowering {
         if (used.count(a) || (!kind && used.count(b))) break;
         used[a] = 1;
         if (!kind) used[b] = 1;
+        if (kind) fbt[s] = (uint32_t)prog.targets.size();
         prog.targets.push_back(a);
         prog.targets.push_back(kind ? (b & ~TGT_REC) : b);
         s++;
@@ -352,6 +356,17 @@ struct Walker {
   std::vector<uint64_t> pending;      // per qubit: site awaiting a verdict (or NONE)
   std::vector<uint8_t> site_live;     // per target index; then n init sites
   static constexpr uint64_t NONE = ~0ull;
+  // Local feedback: per qubit the instruction that last acted on it; per
+  // measurement its qubit, instruction and whether it was a plain M; per
+  // controlled pair's qubit word whether every execution was local.
+  // The last fb_window measurements are kept (a ring; fb_window = the
+  // largest lookback of a controlled pair up to a cap, 0 without feedback).
+  uint64_t clock = 0, fb_window = 0;
+  std::vector<uint64_t> last_touch;
+  std::vector<uint32_t> meas_qubit;
+  std::vector<uint64_t> meas_clock;
+  std::vector<uint8_t> meas_plain;
+  std::vector<uint8_t> fb_local;      // per target index (1 until an execution is not local)
 
   void touch(uint32_t q, bool overwrites_z, uint64_t new_site) {
     if (pending[q] != NONE && !overwrites_z) site_live[pending[q]] = 1;
@@ -365,6 +380,7 @@ struct Walker {
         continue;
       }
       flat++;
+      clock++;
       Program &P = L.prog;
       switch (n.gate) {
         case G_DETECTOR:
@@ -390,7 +406,16 @@ struct Walker {
           break;
         case G_R: case G_M: case G_MR: {
           const std::vector<uint32_t> &tid = L.slot_targets.at(&n);
-          for (size_t s = 0; s < n.targets.size(); s++) touch(n.targets[s], n.gate != G_M, tid[s]);
+          for (size_t s = 0; s < n.targets.size(); s++) {
+            touch(n.targets[s], n.gate != G_M, tid[s]);
+            last_touch[n.targets[s]] = clock;
+            if (n.gate != G_R && fb_window > 0) {
+              const size_t r = (size_t)((meas + s) % (fb_window + 1));
+              meas_qubit[r] = n.targets[s];
+              meas_clock[r] = clock;
+              meas_plain[r] = n.gate == G_M;
+            }
+          }
           if (n.gate != G_R) meas += n.targets.size();
           P.num_gate_targets += n.targets.size();
           break;
@@ -398,6 +423,7 @@ struct Walker {
         default:
           if (gate_is_noise(n.gate)) {
             P.num_noise_targets += n.targets.size() / (gate_is_two_qubit(n.gate) ? 2 : 1);
+            for (uint32_t q : n.targets) last_touch[q] = clock;
           } else if (gate_is_clifford(n.gate)) {
             for (uint32_t q : n.targets) {
               if (q & TGT_REC) {
@@ -406,6 +432,31 @@ struct Walker {
                 continue;
               }
               touch(q, false, NONE);
+            }
+            auto fbt = L.fb_targets.find(&n);
+            if (fbt != L.fb_targets.end()) {
+              // Pairs in line order (the order the ops run in).  A controlled
+              // pair (qubit q, record k) is local when record k is a plain M
+              // of q and nothing has acted on q since -- not even an earlier
+              // pair of this line.
+              for (size_t i = 0; i < fbt->second.size(); i++) {
+                uint32_t a = n.targets[2 * i], b = n.targets[2 * i + 1];
+                if (fbt->second[i] == 0xFFFFFFFFu) {
+                  last_touch[a] = last_touch[b] = clock;
+                  continue;
+                }
+                if (a & TGT_REC) std::swap(a, b);
+                const uint64_t k = b & ~TGT_REC;
+                bool local = k <= fb_window;
+                if (local) {
+                  const size_t r = (size_t)((meas - k) % (fb_window + 1));
+                  local = meas_qubit[r] == a && meas_plain[r] && last_touch[a] == meas_clock[r];
+                }
+                if (!local) fb_local[fbt->second[i]] = 0;
+                last_touch[a] = clock;
+              }
+            } else {
+              for (uint32_t q : n.targets) last_touch[q] = clock;
             }
             P.num_gate_targets += n.targets.size() / (gate_is_two_qubit(n.gate) ? 2 : 1);
           }
@@ -495,6 +546,19 @@ Program compile_program(const std::vector<Node> &tree) {
   w.pending.assign(n, Walker::NONE);
   size_t ntar = L.prog.targets.size();
   w.site_live.assign(ntar, 0);
+  w.last_touch.assign(n, 0);
+  w.fb_local.assign(ntar, 1);
+  // Largest lookback of a controlled pair (capped: longer ones stay global).
+  for (const auto &kv : L.fb_targets)
+    for (size_t i = 0; i < kv.second.size(); i++)
+      if (kv.second[i] != 0xFFFFFFFFu) {
+        const uint32_t a = kv.first->targets[2 * i], b = kv.first->targets[2 * i + 1];
+        const uint64_t k = ((a & TGT_REC) ? a : b) & ~TGT_REC;
+        w.fb_window = std::max<uint64_t>(w.fb_window, std::min<uint64_t>(k, 1u << 16));
+      }
+  w.meas_qubit.assign(w.fb_window + 1, 0);
+  w.meas_clock.assign(w.fb_window + 1, ~0ull);
+  w.meas_plain.assign(w.fb_window + 1, 0);
   for (uint64_t q = 0; q < n; q++) w.pending[q] = q;     // init sites = target slots 0..n-1
   L.prog.det_offsets.push_back(0);
   w.walk(tree);
@@ -575,6 +639,18 @@ Program compile_program(const std::vector<Node> &tree) {
         all_live = false;
       }
     if (all_live) op.code |= OPF_ZRAND_LIVE;
+  }
+  // Mark local feedback pairs, and the feedback ops whose pairs all are.
+  for (DevOp &op : L.prog.ops) {
+    const uint32_t code = op.code & 0xFFFF;
+    if (code < OP_FB_X || code > OP_FB_Z) continue;
+    bool all_local = true;
+    for (uint32_t k = 0; k < op.n; k++) {
+      const size_t t = op.toff + 2 * (size_t)k;
+      if (w.fb_local[t]) L.prog.targets[t] |= TGT_FB_LOCAL;
+      else all_local = false;
+    }
+    if (all_local && op.n > 0) op.code |= OPF_FB_LOCAL;
   }
   return L.prog;
 }

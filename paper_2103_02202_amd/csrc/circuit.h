@@ -68,6 +68,13 @@ constexpr uint32_t OPF_ZRAND_LIVE = 1u << 17;
 // before it is overwritten, so it need not be drawn.
 constexpr uint32_t TGT_DEAD_ZRAND = 1u << 31;
 constexpr uint32_t TGT_QUBIT_MASK = ~TGT_DEAD_ZRAND;
+// Flag on the qubit word of a classically controlled pair (same bit as
+// TGT_DEAD_ZRAND, which only collapse targets carry): the controlling result
+// is a Z measurement of this same qubit, and nothing has acted on the qubit
+// since, so the result's flip is the qubit's current frame x bit.
+constexpr uint32_t TGT_FB_LOCAL = 1u << 31;
+// Flag in OpCode word of a classically controlled op: every pair is local.
+constexpr uint32_t OPF_FB_LOCAL = 1u << 18;
 
 // Device program entry (32 bytes).
 struct DevOp {

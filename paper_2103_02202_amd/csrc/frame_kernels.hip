@@ -349,23 +349,32 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
 // frame.  That difference is read back from the record this workgroup wrote
 // (stored result XOR the reference bit): only this workgroup wrote those
 // words, so a workgroup-scope barrier (release and acquire over all memory)
-// and workgroup-scope loads make the stores of every wave visible.
+// and workgroup-scope loads make the stores of every wave visible.  A pair
+// marked local (its result is a plain M of the same qubit, and nothing has
+// acted on the qubit since) takes the difference from the qubit's own frame
+// x bit instead: no barrier over memory and no load; an op whose pairs are
+// all local needs neither.
 template <int T, bool IN_LDS>
 __device__ __forceinline__ void feedback_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                             uint32_t code, uint64_t meas) {
-  __syncthreads();
+  if (!(op.code & OPF_FB_LOCAL)) __syncthreads();
   const uint32_t items = op.n * T;
   const uint32_t *tg = p.targets + op.toff;
   for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
     const uint32_t k = it / T;
     const int j = (int)(it % T);
     if (j >= tl.valid) continue;
-    const uint32_t q = tg[2 * k];
-    const uint64_t m = meas - tg[2 * k + 1];
-    uint64_t f = __hip_atomic_load(p.out + m * p.out_stride + tl.tw0 + j, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (p.ref != nullptr && ((p.ref[m >> 6] >> (m & 63)) & 1)) f = ~f;
+    const uint32_t qw = tg[2 * k];
+    const uint32_t q = qw & ~TGT_FB_LOCAL;
     const auto ix = tl.at(q, j);
+    uint64_t f;
+    if (qw & TGT_FB_LOCAL) {
+      f = tl.FX[ix];                            // this item's own cell
+    } else {
+      const uint64_t m = meas - tg[2 * k + 1];
+      f = __hip_atomic_load(p.out + m * p.out_stride + tl.tw0 + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (p.ref != nullptr && ((p.ref[m >> 6] >> (m & 63)) & 1)) f = ~f;
+    }
     if (code != OP_FB_Z) tl.FX[ix] ^= f;
     if (code != OP_FB_X) tl.FZ[ix] ^= f;
   }

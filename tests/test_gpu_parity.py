@@ -295,3 +295,31 @@ def test_feedback_lookback_across_repeat_iterations(sg):
             check_meas(sg, text, 3, 3000)
         finally:
             del os.environ["STIM_TILE_WORDS"], os.environ["STIM_FRAME_PLACEMENT"]
+
+
+# Controlled Paulis whose result is a plain M of the same qubit, untouched
+# since, take the flip from the qubit's frame instead of the stored record;
+# everything else reads the record.  Each case against the oracle, with noise
+# before the measurement so that flips are frequent.
+LOCALITY_CASES = {
+    "local_x": "X_ERROR(0.3) 0\nM 0\nCX rec[-1] 0\nM 0\n",
+    "local_y": "H 0\nX_ERROR(0.3) 0\nM 0\nCY rec[-1] 0\nH 0\nM 0\n",
+    "local_z": "X_ERROR(0.3) 0\nM 0\nCZ rec[-1] 0\nH 0\nM 0\n",
+    "double_measure": "X_ERROR(0.3) 0\nM 0 0\nCX rec[-2] 0\nM 0\n",
+    "pauli_gate_between": "X_ERROR(0.3) 0\nM 0\nX 0\nCX rec[-1] 0\nM 0\n",
+    "noise_between": "X_ERROR(0.3) 0\nM 0\nX_ERROR(0.4) 0\nCX rec[-1] 0\nM 0\n",
+    "clifford_between": "X_ERROR(0.3) 0 1\nM 0\nCX 1 0\nCX rec[-1] 0\nM 0 1\n",
+    "earlier_pair_same_line": "X_ERROR(0.3) 0 1\nM 0\nCX 1 0 rec[-1] 0\nM 0 1\n",
+    "later_pair_same_line": "X_ERROR(0.3) 0 1\nM 0\nCX rec[-1] 0 1 0\nM 0 1\n",
+    "mr_source": "X_ERROR(0.3) 0\nMR 0\nX_ERROR(0.3) 0\nCX rec[-1] 0\nM 0\n",
+    "other_qubit": "X_ERROR(0.3) 0\nM 0\nCX rec[-1] 1\nM 0 1\n",
+    "mixed_op": "X_ERROR(0.3) 0 1 2\nM 0 1\nX_ERROR(0.2) 1\nCX rec[-2] 0 rec[-1] 1 rec[-2] 2\nM 0 1 2\n",
+    "loop_local_then_not": ("X_ERROR(0.3) 0 1\nM 0\nREPEAT 5 {\n  CX rec[-1] 0\n  X_ERROR(0.2) 0 1\n  M 1 0\n"
+                            "  CX 0 1\n}\nM 0 1\n"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LOCALITY_CASES))
+def test_feedback_local_and_global_pairs(sg, name):
+    announce("feedback locality", name)
+    check_meas(sg, LOCALITY_CASES[name], 21, 64 * 37 + 5)
