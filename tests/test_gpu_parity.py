@@ -323,3 +323,22 @@ LOCALITY_CASES = {
 def test_feedback_local_and_global_pairs(sg, name):
     announce("feedback locality", name)
     check_meas(sg, LOCALITY_CASES[name], 21, 64 * 37 + 5)
+
+
+def test_feedback_reset_surface_d49_sampled_slices(sg):
+    """The feedback-reset d=49 workload at the benchmark's size (65,536
+    shots, local controlled pairs throughout), checked on sampled words of
+    the record and of the detection events."""
+    announce("feedback reset d49")
+    shots = 65536
+    text = wl.surface_code(49, 49, 1e-3, feedback_reset=True)
+    c = sg.Circuit(text)
+    o = oracle.Circuit(text)
+    full = c.sample(5, shots)
+    det, obs = c.detect(5, shots)
+    torch.cuda.synchronize()
+    for w0 in (3, 1000):
+        want = o.sample(5, 64 * w0, 64, meas=True, det=True, obs=True)
+        assert np.array_equal(full[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["meas"])
+        assert np.array_equal(det[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["det"])
+        assert np.array_equal(obs[:, w0:w0 + 1].cpu().numpy().view(np.uint64), want["obs"])
