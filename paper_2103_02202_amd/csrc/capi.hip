@@ -1337,6 +1337,12 @@ int stim_format_shots(const uint64_t *table, uint64_t rows, uint64_t num_shots, 
     if (*out_len == 0) return STIM_OK;
   }
   hipError_t e;
+  if (format == STIM_FORMAT_B8 && ((rows + 7) / 8) % 4 == 0) {
+    // b8 is the transposed bits with each shot's row cut to ceil(rows / 8)
+    // bytes; when that is a multiple of 4, the transpose writes it directly.
+    e = launch_transpose_b8(table, rows, W, num_shots, out, s);
+    return e == hipSuccess ? STIM_OK : hip_error(e, "b8 launch");
+  }
   uint64_t *T = nullptr, *lens = nullptr, *offs = nullptr, *total = nullptr, *sums = nullptr;
   auto release = [&]() {
     void *ptrs[] = {T, lens, offs, total, sums};

@@ -15,6 +15,10 @@ inline uint64_t transpose_stride(uint64_t rows) { return ((rows + 63) / 64 + 3) 
 // (bit i of T[s][c] = row 64 c + i of shot s; rows past the end read as 0).
 hipError_t launch_transpose(const uint64_t *table, uint64_t rows, uint64_t W, uint64_t shots, uint64_t *T,
                             hipStream_t stream);
+// The b8 format in one pass (the transpose writes the bytes itself); needs
+// ceil(rows / 8) a multiple of 4 and a 4-byte aligned `out`.
+hipError_t launch_transpose_b8(const uint64_t *table, uint64_t rows, uint64_t W, uint64_t shots, uint8_t *out,
+                               hipStream_t stream);
 // Dense formats from T: b8 (ceil(rows/8) bytes per shot) or 01 (rows + 1).
 hipError_t launch_dense_format(const uint64_t *T, uint64_t rows, uint64_t shots, int b8, uint8_t *out,
                                hipStream_t stream);

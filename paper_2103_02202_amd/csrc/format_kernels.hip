@@ -57,9 +57,16 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane) {
 // coalesced 128-byte row segments into LDS, then each wave transposes the four
 // 64 x 64 blocks of one word column and writes each shot's four chunks as
 // 32 contiguous bytes (T rows are padded to a multiple of four chunks).
+// B8: instead of T, write the b8 bytes directly -- bytes [32 cg, 32 cg + 32)
+// of shot s's row, clipped to its nbytes, at out + s nbytes (nbytes a
+// multiple of 4, so every piece starts on a 4-byte boundary; other widths go
+// through T and k_b8, since byte stores at unaligned piece ends cost more
+// than the second pass).
+template <bool B8>
 __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__ table, uint64_t rows, uint64_t W,
                                                     uint64_t shots, uint32_t nchunks, uint32_t tstride,
-                                                    uint64_t *__restrict__ T) {
+                                                    uint64_t *__restrict__ T, uint8_t *__restrict__ out,
+                                                    uint64_t nbytes) {
   __shared__ uint64_t tile[256][17];
   const uint32_t ngroups = (nchunks + 3) / 4;
   // Chunk-group-fastest order: workgroups on one XCD at the same time fill
@@ -86,9 +93,26 @@ __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__
   y1.y = transpose64(tile[192 + lane][k], lane);
   const uint64_t s = (w0 + k) * 64 + lane;
   if (s < shots) {
-    V2 *dst = reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * 4);
-    dst[0] = y0;
-    dst[1] = y1;
+    if constexpr (B8) {
+      typedef uint32_t U32x4a __attribute__((ext_vector_type(4), aligned(4)));
+      const uint64_t b0 = (uint64_t)cg * 32;                    // < nbytes: group cg holds row bits
+      uint8_t *row = out + s * nbytes + b0;
+      const uint32_t w[8] = {(uint32_t)y0.x, (uint32_t)(y0.x >> 32), (uint32_t)y0.y, (uint32_t)(y0.y >> 32),
+                             (uint32_t)y1.x, (uint32_t)(y1.x >> 32), (uint32_t)y1.y, (uint32_t)(y1.y >> 32)};
+      if (nbytes - b0 >= 32) {
+        reinterpret_cast<U32x4a *>(row)[0] = U32x4a{w[0], w[1], w[2], w[3]};
+        reinterpret_cast<U32x4a *>(row)[1] = U32x4a{w[4], w[5], w[6], w[7]};
+      } else {
+        const uint32_t nw = (uint32_t)(nbytes - b0) / 4;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++)
+          if (i < nw) reinterpret_cast<uint32_t *>(row)[i] = w[i];
+      }
+    } else {
+      V2 *dst = reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * 4);
+      dst[0] = y0;
+      dst[1] = y1;
+    }
   }
 }
 
@@ -345,8 +369,20 @@ hipError_t launch_transpose(const uint64_t *table, uint64_t rows, uint64_t W, ui
   const uint64_t blocks = ngroups * wblocks;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFull || nchunks > 0x3FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_transpose, dim3((uint32_t)blocks), dim3(1024), 0, stream, table, rows, W, shots,
-                     (uint32_t)nchunks, (uint32_t)transpose_stride(rows), T);
+  hipLaunchKernelGGL(k_transpose<false>, dim3((uint32_t)blocks), dim3(1024), 0, stream, table, rows, W, shots,
+                     (uint32_t)nchunks, (uint32_t)transpose_stride(rows), T, (uint8_t *)nullptr, (uint64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_b8(const uint64_t *table, uint64_t rows, uint64_t W, uint64_t shots, uint8_t *out,
+                               hipStream_t stream) {
+  const uint64_t nchunks = (rows + 63) / 64, ngroups = (nchunks + 3) / 4, wblocks = (W + 15) / 16;
+  const uint64_t blocks = ngroups * wblocks, nbytes = (rows + 7) / 8;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFull || nchunks > 0x3FFFFFFFull || nbytes % 4 || (uintptr_t)out % 4)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose<true>, dim3((uint32_t)blocks), dim3(1024), 0, stream, table, rows, W, shots,
+                     (uint32_t)nchunks, (uint32_t)transpose_stride(rows), (uint64_t *)nullptr, out, nbytes);
   return hipGetLastError();
 }
 
