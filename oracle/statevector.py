@@ -5,7 +5,7 @@ of ``gates.py``, and exact projective measurement.  Used to pin
 
   * the canonical reference sample (every random measurement, including the one
     hidden in a reset, takes result 0 -- the reading of Sec. 3 / Sec. 4 that
-    this build fixes), and
+    both implementations follow), and
   * the exact distribution of measurement records of noiseless and noisy
     circuits (Pauli channels enumerated), against which the frame sampler's
     empirical distribution is compared.

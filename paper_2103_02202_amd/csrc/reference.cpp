@@ -7,8 +7,8 @@
 // is the column's sign; otherwise the result is random and is resolved by
 // inserting operations at the start of time ("appending"): CNOTs from a pivot
 // onto the other X/Y terms, then H (X term) or H_YZ (Y term) on the pivot, and
-// an X on the pivot when the sign must flip.  This build resolves every random
-// result to 0 (the canonical reference; Sec. 3 makes any noiseless sample a
+// an X on the pivot when the sign must flip.  Every random measurement resolves
+// to 0 here (the canonical reference; Sec. 3 makes any noiseless sample a
 // valid reference).  A reset measures without reporting and then forces the
 // column's sign to +.
 //
