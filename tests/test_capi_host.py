@@ -169,3 +169,6 @@ def test_sample_scratch_bytes(monkeypatch):
     assert c.scratch_bytes(shots, "frame") == 0
     with pytest.raises(sg.StimError):
         sg.stim_sample_scratch_bytes(c.handle, shots, 3)
+    with pytest.raises(sg.StimError):
+        sg.stim_sample_scratch_bytes(0, shots, 0)             # no circuit
+    assert c.scratch_bytes(0, "detector") == 0
