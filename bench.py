@@ -9,8 +9,13 @@ are resident on the GPU before the timed region; compile and reference
 ("analysis") time is reported separately.
 
 Prints one JSON line.  Fields beyond the driver's contract:
-  roofline      -- for the frame kernel, from HIP events on its stream
-  cpu_baseline  -- the oracle timed on this host on a bounded shot sample
+  roofline      -- for the frame kernel (k_frame, HIP events on its stream):
+                   compulsory bytes (the record it writes) against HBM peak,
+                   measured HBM traffic when the counters match the sources
+  cpu_baseline  -- the oracle (-O3 -march=native) timed on this host on a
+                   bounded shot sample, at all usable CPUs and at one
+  configs       -- d=3 x 1,024, d=15 x 2^20 and d=49 x 262,144 shots:
+                   detector- and measurement-mode call times
   analysis_s    -- host compile + reference-sample time
   meas_mode     -- measurement-record sampling (stim_frame_sample) rate
   host_copy     -- copying one step's events to pinned host memory, and the
@@ -42,22 +47,36 @@ sys.path.insert(0, ROOT)
 
 D, ROUNDS, P, SHOTS, SEED = 49, 49, 1e-3, 65536, 0
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the two kernels of one sampling pass at this
-# workload, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per
-# dispatch), scaled by what the same counters read for a plain 2 GiB device
-# copy (python bench.py --copy-probe): FETCH_SIZE reports half the bytes read,
-# WRITE_SIZE all bytes written.  None when the kernels changed after the
-# counters were taken.
+# HBM bytes per launch of k_frame at this workload, from rocprofv3 --pmc
+# FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per dispatch), scaled by what the
+# same counters read for a plain 2 GiB device copy (python bench.py
+# --copy-probe): FETCH_SIZE reports half the bytes read, WRITE_SIZE all bytes
+# written.  The counters hold for the library sources whose digest is
+# PMC_SOURCES; once any of them changes, `traffic` is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-PMC_KIB = {"k_noise_gen": (66095.8, 1025649.2), "k_frame": (360700.0, 1011457.6)}
+PMC_KIB = None                 # {"k_frame": (FETCH_SIZE KiB, WRITE_SIZE KiB)}
+PMC_SOURCES = None             # sources_digest() when the counters were taken
+PMC_PROFILE = "profiles/k_frame_surface_d49_65536shots.md"
+
+
+def sources_digest() -> str:
+    """Digest of the library sources (kernels, compiler, C ABI)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2103_02202_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def streaming_bytes(d: int, rounds: int, p: float, shots: int) -> float:
-    """Algorithmic bytes of the paper's per-op method on the rotated surface
-    code (each operation reads and writes its frame rows in memory, Sec. 5.1):
+    """Bytes the paper's per-op method would move on the rotated surface code
+    (each operation reads and writes its frame rows in memory, Sec. 5.1):
     bits per shot for R 2, H 4, CX 6, M 4 (x read, record write, z read and
     write), dense noise on the 64-shot words an error touches (DEPOLARIZE1 4,
-    DEPOLARIZE2 8, X_ERROR 2)."""
+    DEPOLARIZE2 8, X_ERROR 2).  Here the frame stays on chip, so this is an
+    upper bound on useful traffic, not what the kernel moves."""
     A, data, cx = d * d - 1, d * d, d * (d - 1)
     hit = 1 - (1 - p) ** 64
     per_round = A * 2 + 2 * (A // 2) * 4 + 4 * cx * 6 + A * 4
@@ -66,27 +85,114 @@ def streaming_bytes(d: int, rounds: int, p: float, shots: int) -> float:
     return bits * shots / 8
 
 
-def cpu_baseline(text: str, num_gate_targets: int, budget_s: float = 12.0, threads: int | None = None):
-    """The oracle as it stands, timed on the host cores over a bounded sample
-    of the same workload (first shots of the run, doubling until ~budget)."""
+def host_cpu():
+    """CPU model, logical CPUs, CPUs this process may run on and the cgroup
+    CPU quota (None if unlimited)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()
+            if q != "max":
+                quota = max(1, int(int(q) / int(period)))
+    except (OSError, ValueError):
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "cgroup_cpus": quota}
+
+
+def cpu_baseline(text: str, num_gate_targets: int, budget_s: float = 10.0):
+    """The oracle as it stands (g++ -O3 -march=native build of the same
+    source, OpenMP over 64-shot words), timed on this host over a bounded
+    sample of the same workload: the first shots of the run, doubling until
+    about budget_s / 2 per measurement; at one thread and at every CPU this
+    process may use.  Its single-threaded reference-sample time is reported
+    beside it."""
+    import tempfile
     import oracle
-    threads = threads or min(16, os.cpu_count() or 1)
+    cpu = host_cpu()
+    cores = cpu["affinity"]
+    if cpu["cgroup_cpus"]:
+        cores = min(cores, cpu["cgroup_cpus"])
+    oracle.use_native_build(os.path.join(tempfile.gettempdir(), f"liboracle_native_{os.getpid()}.so"))
     c = oracle.Circuit(text)
     t0 = time.perf_counter()
     ref = c.reference()
     ref_s = time.perf_counter() - t0
-    shots = 256
-    while True:
-        t0 = time.perf_counter()
-        c.sample(SEED, 0, shots, ref=ref, meas=False, det=True, obs=True, threads=threads)
-        dt = time.perf_counter() - t0
-        if dt * 2 > budget_s / 2 or shots >= SHOTS:
-            break
-        shots *= 2
-    return {"value": num_gate_targets * shots / dt, "unit": "shot-gates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"d={D} surface code, shots [0, {shots}) of the {SHOTS}-shot run, detector mode, "
-                      f"{dt:.2f} s sampling; reference sample {ref_s:.2f} s single-threaded"}
+
+    def rate(threads):
+        shots = 256
+        while True:
+            t0 = time.perf_counter()
+            c.sample(SEED, 0, shots, ref=ref, meas=False, det=True, obs=True, threads=threads)
+            dt = time.perf_counter() - t0
+            if dt * 2 > budget_s / 2 or shots >= SHOTS:
+                return shots, dt
+            shots *= 2
+
+    s1, t1 = rate(1)
+    sn, tn = rate(cores)
+    return {"value": num_gate_targets * sn / tn, "unit": "shot-gates/s", "cores": cores, "kind": "oracle",
+            "sample": f"d={D} surface code, shots [0, {sn}) of the {SHOTS}-shot run, detector mode, "
+                      f"{tn:.2f} s sampling on {cores} threads; reference sample {ref_s:.2f} s single-threaded",
+            "one_core": {"value": num_gate_targets * s1 / t1, "shots": s1, "seconds": t1},
+            "build": "g++ -std=c++17 -O3 -march=native -fopenmp", "host": cpu, "reference_s": ref_s}
+
+
+def time_calls(fn, reps, stream):
+    """Average milliseconds per call of fn() over `reps` calls, HIP events on
+    the stream the calls enqueue on (after two warm-up calls)."""
+    import torch
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_configs(stream):
+    """The other single-circuit configurations: d=3 (3 rounds, 1,024 shots),
+    d=15 (15 rounds, 2^20 shots) and d=49 at 262,144 shots (a 315 MB frame,
+    larger than the last-level cache), p = 1e-3, seed 0: detector-mode and
+    measurement-mode call times."""
+    import torch
+    from paper_2103_02202_amd import stim_gpu, workloads
+    out = {}
+    for d, rounds, shots, reps in ((3, 3, 1024, 200), (15, 15, 1 << 20, 5), (49, 49, 1 << 18, 3)):
+        c = stim_gpu.Circuit(workloads.surface_code(d, rounds, P))
+        c.reference()
+        W = (shots + 63) // 64
+        det = torch.empty((c.num_detectors, W), dtype=torch.int64, device="cuda")
+        obs = torch.empty((max(c.num_observables, 1), W), dtype=torch.int64, device="cuda")
+        det_ms = time_calls(lambda: stim_gpu.stim_detector_sample(c.handle, SEED, 0, shots, det, obs, stream),
+                            reps, stream)
+        del det, obs
+        meas = torch.empty((c.num_measurements, W), dtype=torch.int64, device="cuda")
+        meas_ms = time_calls(lambda: stim_gpu.stim_frame_sample(c.handle, SEED, 0, shots, meas, stream), reps,
+                             stream)
+        del meas
+        torch.cuda.empty_cache()
+        G = c.num_gate_targets
+        out[f"d={d}"] = {"workload": f"rotated surface-code Z memory d={d}, {rounds} rounds, p={P}, {shots} shots",
+                         "gate_targets": G, "shots": shots, "detector_ms": det_ms,
+                         "detector_shot_gates_per_s": G * shots / (det_ms * 1e-3), "measurement_ms": meas_ms,
+                         "measurement_shot_gates_per_s": G * shots / (meas_ms * 1e-3),
+                         "record_bytes": c.num_measurements * W * 8,
+                         "record_hbm_frac": c.num_measurements * W * 8 / (meas_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def bench_host_copy(det, obs, stream, ms_per_step, G):
@@ -314,6 +420,7 @@ def main():
     ap.add_argument("--no-feedback", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--sparse-probe", type=float, default=None, metavar="P",
                     help="only run sparse detection sampling of the d=49 workload at noise P, 5 times "
                          "(for profiling)")
@@ -408,12 +515,28 @@ def main():
     stim_gpu.stim_kernel_timing(False)
     pass_ms = ev0.elapsed_time(ev1) / reps
     gen_ms, kframe_ms = gen_ms / passes, kframe_ms / passes
+    # Dominant kernel: k_frame.  Its algorithmic bytes are the compulsory
+    # ones, the measurement record it writes (M S / 8 bytes: one bit per
+    # measurement and shot; the frame stays on chip).
     record_bytes = M * SHOTS / 8
-    alg_bytes = streaming_bytes(D, ROUNDS, P, SHOTS)
-    achieved = alg_bytes / (pass_ms * 1e-3) / 1e9
+    per_op_bytes = streaming_bytes(D, ROUNDS, P, SHOTS)
+    achieved = record_bytes / (kframe_ms * 1e-3) / 1e9
+    digest = sources_digest()
+    fresh = PMC_KIB is not None and PMC_SOURCES == digest
     traffic = None
-    if PMC_KIB:
-        traffic = sum(1024 * (f * FETCH_SCALE + w * WRITE_SCALE) for f, w in PMC_KIB.values())
+    if fresh:
+        f, w = PMC_KIB["k_frame"]
+        traffic = 1024 * (f * FETCH_SCALE + w * WRITE_SCALE)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_frame (measurement mode)",
+                "launch_ms": kframe_ms, "algorithmic_bytes": record_bytes,
+                "algorithmic_bytes_basis": "compulsory: the measurement record, M*S/8 bytes (frame kept in LDS)",
+                "measured_hbm_frac": (traffic / (kframe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                "traffic_over_algorithmic": (traffic / record_bytes) if traffic else None,
+                "per_op_streaming_bytes": per_op_bytes,
+                "traffic_over_per_op_streaming": (traffic / per_op_bytes) if traffic else None,
+                "pass_ms": pass_ms, "k_noise_gen_ms": gen_ms,
+                "counters": PMC_PROFILE if fresh else f"none for library sources {digest}"}
 
     out = {
         "metric": "shot-gates/s + HBM GB/s frac of peak; batched/served vs single; p99 latency",
@@ -432,17 +555,7 @@ def main():
                                "detection events + observables", "d": D, "rounds": ROUNDS, "p": P,
                    "shots": SHOTS, "seed": SEED, "num_qubits": circ.num_qubits, "gate_targets": G,
                    "measurements": M, "detectors": Dn},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "sampling pass = k_noise_gen + k_frame (measurement mode)",
-                     "pass_ms": pass_ms, "k_noise_gen_ms": gen_ms, "k_frame_ms": kframe_ms,
-                     "algorithmic_bytes": alg_bytes,
-                     "algorithmic_bytes_basis": f"per-op streaming, {alg_bytes / (G * SHOTS):.3f} B per shot-gate",
-                     "k_frame_frac": alg_bytes / (kframe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "measured_hbm_frac": (traffic / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                     "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
-                     "compulsory_bytes": record_bytes,
-                     "compulsory_frac": record_bytes / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "roofline": roofline,
         "meas_mode": {"ms": pass_ms, "shot_gates_per_s": G * SHOTS / (pass_ms * 1e-3)},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
@@ -453,6 +566,8 @@ def main():
         out["feedback"] = bench_feedback(max(3, args.steps // 2), det, obs, stream)
     if not args.no_sparse:
         out["sparse"] = bench_sparse(max(3, args.steps // 2), det, obs, stream)
+    if not args.no_configs:
+        out["configs"] = bench_configs(stream)
     if not args.no_reference:
         out["reference"] = bench_reference()
     if not args.no_batch:

@@ -164,7 +164,17 @@ typedef struct {
 
 /* Samples many requests (different circuits, shot counts and modes) in one
  * persistent launch on `hip_stream`; bit-identical to calling the single-
- * request functions one by one. */
+ * request functions one by one.  A request set seen for the first time runs
+ * as one launch at an untuned (or previously tuned) shot-tile width; the
+ * second submission of the same set (same handles, seeds, shots and output
+ * pointers) times each candidate tile width x workgroup size on it, keeps
+ * the fastest for its shape class (qubit count, total words and request
+ * count, each rounded up to a power of two) and captures the launch in a HIP
+ * graph that later submissions replay.  Environment: STIM_TUNE=0 skips the
+ * timing trials; STIM_TUNE_CACHE=<file> keeps tuned shape classes across
+ * processes (read on the first batched call, appended as classes are tuned).
+ * A tuned width is reused only where the request set's largest frame fits
+ * in LDS at that width. */
 int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream);
 
 /* Shot-major output formats (Sec. 5.11, "Output Format"). */

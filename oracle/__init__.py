@@ -24,18 +24,34 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles oracle.cpp into liboracle.so with g++ (-O2, OpenMP)."""
+def build(verbose: bool = False, native: bool = False, path: str | None = None) -> str:
+    """Compiles oracle.cpp into liboracle.so with g++ (-O2, OpenMP).
+
+    native=True builds the same source with -O3 -march=native for the host it
+    runs on (into `path`), the build the CPU baseline is timed with; the code
+    is unchanged, only the compiler flags differ."""
     src = os.path.join(_HERE, "oracle.cpp")
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-shared", "-fPIC", src, "-o", tmp]
+    out = path or _LIB_PATH
+    tmp = out + ".tmp"
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["g++", "-std=c++17", *opt, "-fopenmp", "-shared", "-fPIC", src, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + res.stderr)
-    os.replace(tmp, _LIB_PATH)
+    os.replace(tmp, out)
     if verbose:
-        print("built", _LIB_PATH)
-    return _LIB_PATH
+        print("built", out)
+    return out
+
+
+def use_native_build(path: str) -> None:
+    """Builds the -O3 -march=native copy at `path` and makes this process use
+    it; must be called before the first Circuit is created."""
+    global _lib, _LIB_PATH
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    build(native=True, path=path)
+    _LIB_PATH = path
 
 
 def lib():

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -358,15 +359,20 @@ FrameConfig choose_config(uint64_t n, uint64_t W) {
 
 // Pinned host buffers for uploading per-launch tables without blocking the
 // host: a buffer is reused only after the copy that read it has completed.
+// Sampling calls may come from several host threads at once (one stream
+// each), so the pool is taken under a lock for the whole pick-copy-record
+// sequence.
 struct StagingBuffer {
   void *ptr = nullptr;
   size_t cap = 0;
   hipEvent_t done = nullptr;
   bool busy = false;
 };
+std::mutex g_staging_mu;
 std::vector<StagingBuffer> g_staging;
 
 int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_staging_mu);
   StagingBuffer *buf = nullptr;
   for (StagingBuffer &b : g_staging) {
     if (b.busy && hipEventQuery(b.done) == hipSuccess) b.busy = false;
@@ -378,8 +384,10 @@ int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s) {
     if (!buf) {
       g_staging.emplace_back();
       buf = &g_staging.back();
-      if (hipEventCreateWithFlags(&buf->done, hipEventDisableTiming) != hipSuccess)
+      if (hipEventCreateWithFlags(&buf->done, hipEventDisableTiming) != hipSuccess) {
+        g_staging.pop_back();
         return set_error(STIM_E_DEVICE, "hipEventCreate failed");
+      }
     }
     if (buf->cap < bytes) {
       if (buf->ptr) (void)hipHostFree(buf->ptr);
@@ -503,7 +511,7 @@ uint64_t pass_scratch_bytes(const Program &P, uint64_t num_shots, int dev) {
     if (nrec > 0 && nrec * 16 <= kMaxRecordBytes) bytes += ninst * ntiles * sizeof(uint2) + ninst * 12 + nrec * 16;
   }
   if (!cfg.in_lds)
-    bytes += global_frame_slots(dev, ntiles) * cfg.tile_words * 16 * std::max<uint64_t>(P.num_qubits, 1);
+    bytes += global_frame_slots(dev, ntiles) * cfg.tile_words * 16 * (P.num_qubits + 1);
   return bytes;
 }
 
@@ -635,7 +643,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     (void)hipGetDevice(&dev);
     cfg.slots = (uint32_t)global_frame_slots(dev, ntiles);
     const uint64_t tiles = cfg.slots;
-    size_t bytes = (size_t)tiles * cfg.tile_words * 16 * std::max<uint64_t>(c->prog.num_qubits, 1);
+    size_t bytes = (size_t)tiles * cfg.tile_words * 16 * (c->prog.num_qubits + 1);     // + the dummy row
     if ((e = hipMallocAsync((void **)&p.scratch, bytes, s)) != hipSuccess) {
       free_prepass();
       drop_events();
@@ -721,6 +729,38 @@ std::mutex g_batch_mu;
 std::vector<std::unique_ptr<BatchPlan>> g_plans;           // most recent last
 std::map<std::string, FrameConfig> g_tuned;                // shape class -> config
 std::vector<uint64_t> g_seen;                               // signatures of recent one-shot request sets
+std::string g_tune_cache_read;                              // cache file last read
+
+// Tuned configurations persist across processes in the text file named by
+// STIM_TUNE_CACHE (one "class tile_words threads" line per tuned shape class;
+// a later line for a class wins).  Read by the first batched launch that sees
+// the variable name that file; each newly tuned class is appended.  Called
+// with g_batch_mu held.
+void load_tune_cache() {
+  const char *path = std::getenv("STIM_TUNE_CACHE");
+  if (!path || !*path || g_tune_cache_read == path) return;
+  g_tune_cache_read = path;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char cls[128];
+  int T = 0;
+  unsigned threads = 0;
+  while (std::fscanf(f, "%127s %d %u", cls, &T, &threads) == 3) {
+    if ((T == 1 || T == 2 || T == 4 || T == 8) && threads >= 64 && threads <= 1024 && threads % 64 == 0)
+      g_tuned[cls] = FrameConfig{T, true, threads};
+  }
+  std::fclose(f);
+}
+
+void save_tuned(const std::string &cls, const FrameConfig &cfg) {
+  g_tuned[cls] = cfg;
+  const char *path = std::getenv("STIM_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE *f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %u\n", cls.c_str(), cfg.tile_words, cfg.threads);
+    std::fclose(f);
+  }
+}
 
 void free_plan(BatchPlan *pl) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
@@ -807,6 +847,17 @@ bool same_request(const stim_request &a, const stim_request &b) {
 
 bool batch_fits(uint64_t n, int T, uint32_t threads) {
   return frame_lds_bytes(n, T, true, threads) + kBatchStaticLds <= kMaxLdsBytes;
+}
+
+// The tuned configuration of a plan's shape class, if there is one that fits
+// this plan: a class spans a factor of two in qubit count, so a width tuned
+// for its smaller circuits may not fit the LDS of its larger ones.
+std::string shape_class(const BatchPlan &pl);
+bool tuned_config(const BatchPlan &pl, FrameConfig *cfg) {
+  auto known = g_tuned.find(shape_class(pl));
+  if (known == g_tuned.end() || !batch_fits(pl.max_n, known->second.tile_words, known->second.threads)) return false;
+  *cfg = known->second;
+  return true;
 }
 
 std::string shape_class(const BatchPlan &pl) {
@@ -957,8 +1008,8 @@ FrameConfig untuned_batch_config(uint64_t max_n) {
 int run_one_shot(BatchPlan &pl, hipStream_t s) {
   uint64_t total_flips = partition_requests(pl);
   if (pl.batched.empty()) return STIM_OK;
-  auto known = g_tuned.find(shape_class(pl));
-  pl.cfg = known != g_tuned.end() ? known->second : untuned_batch_config(pl.max_n);
+  load_tune_cache();
+  if (!tuned_config(pl, &pl.cfg)) pl.cfg = untuned_batch_config(pl.max_n);
   std::vector<BatchItem> items = work_list(pl, pl.cfg.tile_words);
   pl.num_items = (uint32_t)items.size();
   pl.blocks = (uint32_t)(cu_count(pl.device) * batch_blocks_per_cu(pl.cfg, pl.max_n));
@@ -1005,8 +1056,9 @@ int build_plan(BatchPlan &pl, hipStream_t s) {
   const char *tune_env = std::getenv("STIM_TUNE");
   const bool tune = !(tune_env && std::strcmp(tune_env, "0") == 0);
   const std::string cls = shape_class(pl);
-  auto known = g_tuned.find(cls);
-  if (known != g_tuned.end()) cands = {known->second};
+  load_tune_cache();
+  FrameConfig known;
+  if (tuned_config(pl, &known)) cands = {known};
   else if (!tune) cands = {untuned_batch_config(pl.max_n)};
 
   std::vector<int> widths;
@@ -1063,7 +1115,7 @@ int build_plan(BatchPlan &pl, hipStream_t s) {
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    g_tuned[cls] = best_cfg;
+    save_tuned(cls, best_cfg);
     pl.tuned_ms = best;
   }
   pl.cfg = best_cfg;

@@ -236,6 +236,7 @@ struct Lowering {
     const OpCode quantum = opcode(n.gate);
     const OpCode fb = n.gate == G_CX ? OP_FB_X : n.gate == G_CY ? OP_FB_Y : OP_FB_Z;
     const size_t pairs = n.targets.size() / 2;
+    if (prog.targets.size() % 2) prog.targets.push_back(0);     // pairs start on an even index
     std::vector<uint32_t> &fbt = fb_targets[&n];
     fbt.assign(pairs, 0xFFFFFFFFu);
     std::unordered_map<uint32_t, int> used;
@@ -283,6 +284,9 @@ struct Lowering {
       return;
     }
     int k = gate_is_two_qubit(n.gate) ? 2 : 1;
+    // Pairs start on an even index, so that a kernel reads a pair as one
+    // 8-byte word; the padding word belongs to no op.
+    if (k == 2 && prog.targets.size() % 2) prog.targets.push_back(0);
     uint32_t aux = gate_is_noise(n.gate) ? threshold_row(n.p) : 0;
     size_t slots = n.targets.size() / k;
     bool collapse = code == OP_R || code == OP_M || code == OP_MR;

@@ -72,7 +72,8 @@ struct FrameConfig {
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Dynamic LDS of one frame workgroup: a 64-entry queue per wave, one
-// 64-entry threshold row, plus the frame slice (16 n T bytes) when it is held
+// 64-entry threshold row, plus the frame slice (16 (n + 1) T bytes: the
+// qubits and a dummy row) when it is held
 // in LDS.
 size_t frame_lds_bytes(uint64_t n, int T, bool in_lds, uint32_t threads);
 

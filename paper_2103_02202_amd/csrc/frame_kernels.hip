@@ -8,9 +8,10 @@
 // barrier separates consecutive ops.
 //
 // The frame slice of a tile holds T X words and T Z words per qubit (bit j of
-// word w = shot 64 (tile word w) + j).  It lives in LDS when 16 n T bytes
-// fit, as two planes X then Z, each [n][T]; otherwise in a global scratch
-// buffer as [n][2][T] (a qubit's X and Z words adjacent).
+// word w = shot 64 (tile word w) + j), plus one dummy row past the last qubit
+// that absorbs the writes of idle lanes.  It lives in LDS when 16 (n + 1) T
+// bytes fit, as two planes X then Z, each [n + 1][T]; otherwise in a global
+// scratch buffer as [n + 1][2][T] (a qubit's X and Z words adjacent).
 //
 // Random bits are drawn cooperatively: a lane evaluates one Philox call for a
 // group of slots on one word -- four slots for Z randomisation, thirty-two
@@ -23,6 +24,7 @@
 
 #include "circuit.h"
 #include "frame_kernels.h"
+#include "lds_attr.h"
 #include "rng.h"
 
 namespace stimgpu {
@@ -86,6 +88,7 @@ struct Tile {
   uint64_t *queue;            // this wave's 64-entry LDS queue
   uint64_t tw0;               // first local word of the tile
   int valid;                  // words of the tile inside [0, W)
+  uint32_t dummy;             // row past the last qubit: a sink for writes of idle items
 
   __device__ __forceinline__ Index at(uint32_t q, int j) const {
     if constexpr (IN_LDS) return q * (uint32_t)T + (uint32_t)j;
@@ -271,76 +274,95 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
 
 // Clifford ops: one item per (target, pair of words) -- a thread moves two
 // adjacent words of a qubit with one 16-byte LDS access (one word when T = 1).
-// A thread takes up to U items at once and issues all of their target loads
-// and frame reads before any write; the items of one op touch distinct
-// (qubit, word) cells, so this is safe and hides the load latency.  Words of
-// the tile past the end of the shot range are updated too (they belong to no
-// shot and are never written out).  Every thread runs at least one pass, and
-// every load of a pass is issued unconditionally (clamped indices), so that
-// the compiler can wait for exactly the loads it needs.
-template <int T, bool IN_LDS, typename AfterLoads>
+// One instantiation per opcode, so that nothing inside the item loop depends
+// on the opcode at run time: a thread takes up to U items at once, issues
+// every target load of the pass (a pair as one 8-byte load: the compiler
+// starts every two-qubit op's targets on an even index), then every frame
+// read, then the writes.  The items of one op touch distinct (qubit, word)
+// cells, so this is safe.  Words of the tile past the end of the shot range
+// are updated too (they belong to no shot and are never written out).  Every
+// thread runs at least one pass; loads use clamped indices, so they are issued
+// on every path and the compiler waits only for the loads it needs.
+template <int T, bool IN_LDS, uint32_t CODE, typename AfterLoads>
 __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
-                                         uint32_t code, AfterLoads after_loads) {
+                                            AfterLoads after_loads) {
   constexpr int U = 3;
   constexpr uint32_t C = T >= 2 ? 2 : 1;          // words per item
   constexpr uint32_t CPT = T / C;                 // items per target
+  constexpr bool TWO = CODE == OP_CX || CODE == OP_CY || CODE == OP_CZ || CODE == OP_SWAP;
   typedef uint64_t U64x2v __attribute__((ext_vector_type(2)));
   typedef typename std::conditional<C == 2, U64x2v, uint64_t>::type Vec;
-  const bool two = code == OP_CX || code == OP_CY || code == OP_CZ || code == OP_SWAP;
+  typedef typename Tile<T, IN_LDS>::Index Index;
   const uint32_t items = op.n * CPT;
   const uint32_t *tg = p.targets + op.toff;
-  const uint32_t stride = blockDim.x;
-  auto X = [&](typename Tile<T, IN_LDS>::Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FX + i); };
-  auto Z = [&](typename Tile<T, IN_LDS>::Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FZ + i); };
-  uint32_t base = threadIdx.x;
-  do {
-    typename Tile<T, IN_LDS>::Index ia[U], ib[U];
+  const uint32_t per_pass = U * blockDim.x;
+  const uint32_t passes = items > per_pass ? (items + per_pass - 1) / per_pass : 1u;     // uniform
+  auto X = [&](Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FX + i); };
+  auto Z = [&](Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FZ + i); };
+  for (uint32_t pass = 0; pass < passes; pass++) {
+    const uint32_t base = threadIdx.x + pass * per_pass;
+    uint32_t qa[U], qb[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const uint32_t it = base + u * stride;
-      const uint32_t k = it / CPT;
-      const int j = (int)((it % CPT) * C);
+      const uint32_t it = base + u * blockDim.x;
       ok[u] = it < items;
-      const uint32_t kk = ok[u] ? k : 0;
-      const uint32_t qa = tg[two ? 2 * kk : kk];
-      const uint32_t qb = two ? tg[2 * kk + 1] : qa;
-      ia[u] = tl.at(qa, j);
-      ib[u] = tl.at(qb, j);
+      const uint32_t k = ok[u] ? it / CPT : 0u;
+      if constexpr (TWO) {
+        const uint2 pr = *reinterpret_cast<const uint2 *>(tg + 2 * k);
+        qa[u] = pr.x;
+        qb[u] = pr.y;
+      } else {
+        qa[u] = tg[k];
+        qb[u] = 0;
+      }
     }
     after_loads();
+    // Idle items (past the op's last target) read a real row and write the
+    // dummy row, so that no access is predicated.
+    Index ra[U], rb[U], wa[U], wb[U];
     Vec xa[U], za[U], xb[U], zb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      if (!ok[u]) continue;
-      xa[u] = X(ia[u]);
-      za[u] = Z(ia[u]);
-      if (two) {
-        xb[u] = X(ib[u]);
-        zb[u] = Z(ib[u]);
+      const int j = (int)(((base + u * blockDim.x) % CPT) * C);
+      ra[u] = tl.at(qa[u], j);
+      rb[u] = tl.at(qb[u], j);
+      wa[u] = ok[u] ? ra[u] : tl.at(tl.dummy, j);
+      wb[u] = ok[u] ? rb[u] : tl.at(tl.dummy, j);
+      xa[u] = X(ra[u]);
+      za[u] = Z(ra[u]);
+      if constexpr (TWO) {
+        xb[u] = X(rb[u]);
+        zb[u] = Z(rb[u]);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      if (!ok[u]) continue;
-      switch (code) {
-        case OP_SWAP_XZ: X(ia[u]) = za[u]; Z(ia[u]) = xa[u]; break;
-        case OP_Z_XOR_X: Z(ia[u]) = za[u] ^ xa[u]; break;
-        case OP_X_XOR_Z: X(ia[u]) = xa[u] ^ za[u]; break;
-        case OP_CX: X(ib[u]) = xb[u] ^ xa[u]; Z(ia[u]) = za[u] ^ zb[u]; break;
-        case OP_CZ: Z(ia[u]) = za[u] ^ xb[u]; Z(ib[u]) = zb[u] ^ xa[u]; break;
-        case OP_CY:
-          X(ib[u]) = xb[u] ^ xa[u];
-          Z(ib[u]) = zb[u] ^ xa[u];
-          Z(ia[u]) = za[u] ^ xb[u] ^ zb[u];
-          break;
-        default:   // SWAP
-          X(ia[u]) = xb[u]; Z(ia[u]) = zb[u]; X(ib[u]) = xa[u]; Z(ib[u]) = za[u];
-          break;
+      if constexpr (CODE == OP_SWAP_XZ) {
+        X(wa[u]) = za[u];
+        Z(wa[u]) = xa[u];
+      } else if constexpr (CODE == OP_Z_XOR_X) {
+        Z(wa[u]) = za[u] ^ xa[u];
+      } else if constexpr (CODE == OP_X_XOR_Z) {
+        X(wa[u]) = xa[u] ^ za[u];
+      } else if constexpr (CODE == OP_CX) {
+        X(wb[u]) = xb[u] ^ xa[u];
+        Z(wa[u]) = za[u] ^ zb[u];
+      } else if constexpr (CODE == OP_CZ) {
+        Z(wa[u]) = za[u] ^ xb[u];
+        Z(wb[u]) = zb[u] ^ xa[u];
+      } else if constexpr (CODE == OP_CY) {
+        X(wb[u]) = xb[u] ^ xa[u];
+        Z(wb[u]) = zb[u] ^ xa[u];
+        Z(wa[u]) = za[u] ^ xb[u] ^ zb[u];
+      } else {   // SWAP
+        X(wa[u]) = xb[u];
+        Z(wa[u]) = zb[u];
+        X(wb[u]) = xa[u];
+        Z(wb[u]) = za[u];
       }
     }
-    base += U * stride;
-  } while (base < items);
+  }
 }
 
 // Classically controlled Pauli (Sec. 3, tracking corrections): for each pair
@@ -594,12 +616,13 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint32_t thr_row = 0xFFFFFFFFu;
   uint64_t *F;
   if constexpr (IN_LDS) F = lds + nwaves * 64 + 64;
-  else F = p.scratch + (size_t)slot * 2 * n * T;
+  else F = p.scratch + (size_t)slot * 2 * (n + 1) * T;
   tl.FX = F;
   // In LDS the X and Z planes are separate (fewer bank conflicts on the
   // strided target patterns); in global memory each qubit's X and Z words
   // are adjacent, so one cache line serves both.
-  tl.FZ = IN_LDS ? F + (size_t)n * T : F + T;
+  tl.FZ = IN_LDS ? F + (size_t)(n + 1) * T : F + T;
+  tl.dummy = n;
   tl.tw0 = (uint64_t)tile * T;
   tl.valid = (int)((p.num_words - tl.tw0) < (uint64_t)T ? (p.num_words - tl.tw0) : (uint64_t)T);
 
@@ -695,7 +718,15 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     } else if (code >= OP_FB_X) {
       feedback_op<T, IN_LDS>(p, tl, op, code, meas);
     } else {
-      clifford_op<T, IN_LDS>(p, tl, op, code, stage_b);
+      switch (code) {
+        case OP_SWAP_XZ: clifford_op<T, IN_LDS, OP_SWAP_XZ>(p, tl, op, stage_b); break;
+        case OP_Z_XOR_X: clifford_op<T, IN_LDS, OP_Z_XOR_X>(p, tl, op, stage_b); break;
+        case OP_X_XOR_Z: clifford_op<T, IN_LDS, OP_X_XOR_Z>(p, tl, op, stage_b); break;
+        case OP_CX: clifford_op<T, IN_LDS, OP_CX>(p, tl, op, stage_b); break;
+        case OP_CY: clifford_op<T, IN_LDS, OP_CY>(p, tl, op, stage_b); break;
+        case OP_CZ: clifford_op<T, IN_LDS, OP_CZ>(p, tl, op, stage_b); break;
+        default: clifford_op<T, IN_LDS, OP_SWAP>(p, tl, op, stage_b); break;
+      }
     }
     if (code == OP_M || code == OP_MR) meas += op.n;
     tile_barrier<IN_LDS>();
@@ -801,19 +832,14 @@ __global__ void __launch_bounds__(256) k_parity(const uint64_t *__restrict__ fli
 // Launchers.
 // ---------------------------------------------------------------------------
 size_t frame_lds_bytes(uint64_t n, int T, bool in_lds, uint32_t threads) {
-  return ((size_t)(threads / 64) * 64 + 64) * sizeof(uint64_t) + (in_lds ? (size_t)16 * n * T : 0);
+  return ((size_t)(threads / 64) * 64 + 64) * sizeof(uint64_t) + (in_lds ? (size_t)16 * (n + 1) * T : 0);
 }
 
 template <int T, bool IN_LDS>
 static hipError_t launch_frame_t(const FrameParams &p, uint32_t tiles, uint32_t threads, size_t lds_bytes,
                                  hipStream_t stream) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_frame<T, IN_LDS>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = allow_dynamic_lds((const void *)k_frame<T, IN_LDS>, (int)kMaxLdsBytes);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_frame<T, IN_LDS>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
   return hipGetLastError();
 }
@@ -843,13 +869,8 @@ hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_
 template <int T>
 static hipError_t launch_batch_t(const FrameParams *reqs, const BatchItem *items, uint32_t num_items,
                                  uint32_t *counter, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t stream) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kMaxLdsBytes - kBatchStaticLds));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = allow_dynamic_lds((const void *)k_batch<T>, (int)(kMaxLdsBytes - kBatchStaticLds));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, counter, 0u);
   hipLaunchKernelGGL((k_batch<T>), dim3(blocks), dim3(threads), lds, stream, reqs, items, num_items, counter);
   return hipGetLastError();

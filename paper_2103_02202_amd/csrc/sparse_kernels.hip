@@ -18,6 +18,7 @@
 // errors of one word can flip the same output.
 #include <hip/hip_runtime.h>
 
+#include "lds_attr.h"
 #include "rng.h"
 #include "sparse_kernels.h"
 
@@ -358,13 +359,8 @@ uint32_t sparse_window_max_rows(int T, uint32_t num_obs) {
 
 template <int T>
 static hipError_t launch_window_t(const SparseWindowParams &p, hipStream_t stream) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_sparse_window<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(160 * 1024 - kWindowStaticLds));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = allow_dynamic_lds((const void *)k_sparse_window<T>, (int)(160 * 1024 - kWindowStaticLds));
+  if (e != hipSuccess) return e;
   const uint64_t tiles = (p.s.num_words + T - 1) / T;
   hipLaunchKernelGGL(k_sparse_window<T>, dim3((uint32_t)tiles), dim3(kWindowThreads),
                      sparse_window_lds_bytes(T, p.win, p.num_obs), stream, p);

@@ -80,6 +80,8 @@ def test_batch_matches_single_requests_and_replays(sg):
     for _ in range(2):
         for r in reqs:
             r["out0"].fill_(-1)
+            if r["out1"] is not None:
+                r["out1"].fill_(-1)
         sg.stim_batch_sample(reqs)
         torch.cuda.synchronize()
         check_against_single(sg, reqs, circs)
@@ -192,3 +194,51 @@ def test_many_noise_executions_fall_back_to_inline(sg):
     assert np.array_equal(reqs[0]["out0"].cpu().numpy().view(np.uint64), want)
     assert want.any()
     check_against_single(sg, reqs, circs)
+
+
+def test_tuned_width_is_not_reused_where_the_frame_does_not_fit(sg, tmp_path, monkeypatch):
+    """A shape class spans a factor of two in qubit count.  A tile width tuned
+    for its smaller circuits (here written into the tuning cache file: 8 words,
+    256 threads for the class of 1,025..2,048 qubits, 64 words, one request)
+    must not be used for a 2,000-qubit circuit, whose frame needs 256 KB of
+    LDS at that width: both the first (one launch) and the second (tuned,
+    captured) submission succeed and equal the single call."""
+    announce("tuned width vs larger circuit of the same class")
+    cache = tmp_path / "tune.txt"
+    cache.write_text("11/6/0 8 256\n")
+    monkeypatch.setenv("STIM_TUNE_CACHE", str(cache))
+    text = wl.random_clifford(2000, 5, seed=17)
+    reqs, circs = make_requests(sg, [(text, 4096, 31, 0, 0)])
+    for _ in range(3):
+        reqs[0]["out0"].fill_(-1)
+        sg.stim_batch_sample(reqs)
+        torch.cuda.synchronize()
+        check_against_single(sg, reqs, circs)
+    # The class was tuned again (its cached width does not fit): a new line.
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and lines[1].startswith("11/6/0 ") and not lines[1].endswith(" 8 256")
+
+
+def test_tuning_cache_file_round_trip(sg, tmp_path, monkeypatch):
+    """Tuned classes are appended to the cache file and read back by a later
+    launch: a class present in the file is not tuned again."""
+    announce("tuning cache round trip")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("STIM_TUNE_CACHE", str(cache))
+    # 17 requests: a shape class no other test of this process submits.
+    specs = [(wl.surface_code(3, 3, 1e-3), 1024, 41 + k, 1, 0) for k in range(16)]
+    specs.append((wl.random_clifford(20, 20, seed=4), 1000, 60, 0, 0))
+    reqs, circs = make_requests(sg, specs)
+    for _ in range(2):
+        sg.stim_batch_sample(reqs)
+        torch.cuda.synchronize()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    cls, T, threads = lines[0].split()
+    assert int(T) in (1, 2, 4, 8) and int(threads) in (256, 512, 1024)
+    reqs2, circs2 = make_requests(sg, specs)         # same class, new outputs: a new plan
+    for _ in range(2):
+        sg.stim_batch_sample(reqs2)
+        torch.cuda.synchronize()
+    check_against_single(sg, reqs2, circs2)
+    assert cache.read_text().splitlines() == lines
