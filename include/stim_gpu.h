@@ -116,6 +116,23 @@ int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint
 int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
                          uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments and results as stim_detector_sample, bit for bit, without any
+ * allocation.  The flip table of the call (and, for circuits whose frame does
+ * not fit in LDS, the frame slots) lives in a device array of 256 MiB that
+ * the library holds on each device it runs on until the process ends; the
+ * noise is drawn inside the frame kernel (no pre-pass records).  Calls that
+ * need more scratch than that (about 8 (num_measurements + 1)
+ * ceil(num_shots / 64) bytes) return STIM_E_UNSUPPORTED: split the shots.
+ * The circuit must already be resident on the current device -- any earlier
+ * allocating sampling call on this device uploads it -- else
+ * STIM_E_INVALID_ARG.  Every call on one device shares that array: calls that
+ * overlap on one device (several streams or threads) race and must be
+ * serialised by the caller. */
+int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
+                                 uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
+
 /* Sparse detection-event sampling (Sec. 5.6: draw the errors, XOR the sets
  * of detectors each one flips).  Same arguments, output layout and results as
  * stim_detector_sample: the errors are drawn from the frame sampler's own

@@ -22,6 +22,15 @@
 
 using namespace stimgpu;
 
+// Device scratch of stim_detector_sample_noalloc: the flip table (and the
+// frame slots of circuits too large for LDS) of one call, in a file-scope
+// device array instead of the stream-ordered pool.  Each device that loads
+// the library holds its own copy until the process ends.  Host code reaches
+// it only through the address hipGetSymbolAddress returns on each device (the
+// array's name on the host is a stand-in, not a device address).
+constexpr size_t kNoAllocScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -1143,6 +1152,26 @@ int build_plan(BatchPlan &pl, hipStream_t s) {
   return STIM_OK;
 }
 
+std::mutex g_noalloc_mu;
+std::map<int, void *> g_noalloc_ptr;      // device -> address of `scratch` there
+
+// Address of `scratch` on device `dev` (the current device), looked up once.
+int noalloc_scratch(int dev, void **out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(dev);
+  if (it != g_noalloc_ptr.end()) {
+    *out = it->second;
+    return STIM_OK;
+  }
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+  if (!ptr) return set_error(STIM_E_DEVICE, "hipGetSymbolAddress(scratch) returned no address");
+  g_noalloc_ptr[dev] = ptr;
+  *out = ptr;
+  return STIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1253,6 +1282,74 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   hipError_t fe = hipFreeAsync(flips, s);
   if (!rc && fe != hipSuccess) rc = hip_error(fe, "hipFreeAsync");
   return rc;
+}
+
+int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
+                                 uint64_t *out_det, uint64_t *out_obs, void *hip_stream) {
+  int rc = check_sample_args(c, shot_offset, num_shots);
+  if (rc) return rc;
+  if (c->prog.num_detectors > 0 && !is_device_pointer(out_det))
+    return set_error(STIM_E_INVALID_ARG, "out_det is not a device pointer");
+  if (out_obs && c->prog.num_observables > 0 && !is_device_pointer(out_obs))
+    return set_error(STIM_E_INVALID_ARG, "out_obs is not a device pointer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  DeviceCopy *d = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    auto it = c->dev.find(dev);
+    if (it == c->dev.end())
+      return set_error(STIM_E_INVALID_ARG, "the circuit is not resident on device " + std::to_string(dev) +
+                                               ": an allocating sampling call on this device uploads it first");
+    d = &it->second;
+  }
+  const Program &P = c->prog;
+  const uint64_t W = (num_shots + 63) / 64;
+  FrameConfig cfg = choose_config(P.num_qubits, W);
+  const uint64_t ntiles = (W + cfg.tile_words - 1) / cfg.tile_words;
+  const uint64_t flip_bytes = (std::max<uint64_t>(P.num_measurements, 1) * W * 8 + 255) / 256 * 256;
+  uint64_t slot_bytes = 0;
+  if (!cfg.in_lds) {
+    cfg.slots = (uint32_t)global_frame_slots(dev, ntiles);
+    slot_bytes = (uint64_t)cfg.slots * cfg.tile_words * 16 * (P.num_qubits + 1);
+  }
+  if (flip_bytes + slot_bytes > kNoAllocScratchBytes)
+    return set_error(STIM_E_UNSUPPORTED, "this call needs " + std::to_string(flip_bytes + slot_bytes) +
+                                             " bytes of device scratch, more than the " +
+                                             std::to_string(kNoAllocScratchBytes) +
+                                             " this entry point holds: sample fewer shots per call");
+  void *base = nullptr;
+  if ((rc = noalloc_scratch(dev, &base))) return rc;
+  uint64_t *flips = (uint64_t *)base;
+  FrameParams p{};
+  p.ops = d->ops;
+  p.num_ops = (uint32_t)P.ops.size();
+  p.num_qubits = (uint32_t)P.num_qubits;
+  p.targets = d->targets;
+  p.thresholds = d->thresholds;
+  p.ref = nullptr;                         // raw flips
+  p.seed = seed;
+  p.word0 = shot_offset / 64;
+  p.num_words = W;
+  const uint64_t rem = num_shots % 64;
+  p.tail_mask = rem ? ((1ull << rem) - 1) : ~0ull;
+  p.out = flips;
+  p.out_stride = W;
+  p.scratch = slot_bytes ? (uint64_t *)((unsigned char *)base + flip_bytes) : nullptr;
+  p.noise_meta = nullptr;                  // noise drawn inline: its records would need more scratch
+  if (P.num_measurements > 0 || P.num_qubits > 0) {
+    if ((e = launch_frame(p, cfg, s)) != hipSuccess) return hip_error(e, "frame kernel launch");
+  }
+  if ((e = launch_parity(flips, W, d->det_off, d->det_idx, d->det_order, (uint32_t)P.num_detectors, out_det, s)) !=
+      hipSuccess)
+    return hip_error(e, "detector kernel launch");
+  if (out_obs &&
+      (e = launch_parity(flips, W, d->obs_off, d->obs_idx, nullptr, (uint32_t)P.num_observables, out_obs, s)) !=
+          hipSuccess)
+    return hip_error(e, "observable kernel launch");
+  return STIM_OK;
 }
 
 int stim_sparse_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,

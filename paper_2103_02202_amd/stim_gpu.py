@@ -47,6 +47,7 @@ def lib():
         L.stim_frame_sample.argtypes = [vp, u64, u64, u64, vp, vp]
         L.stim_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.stim_sparse_detector_sample.argtypes = [vp, u64, u64, u64, vp, vp, vp]
+        L.stim_detector_sample_noalloc.argtypes = [vp, u64, u64, u64, vp, vp, vp]
         L.stim_reference_sample_gpu.argtypes = [vp, vp, vp]
         L.stim_error_sets.argtypes = [vp, P64, P64, vp, vp]
         L.stim_sample_scratch_bytes.argtypes = [vp, u64, ctypes.c_int, P64]
