@@ -427,6 +427,9 @@ def main():
     ap.add_argument("--reference-probe", type=int, default=None, metavar="D",
                     help="only compute the GPU reference sample of the distance-D surface code twice "
                          "(for profiling)")
+    ap.add_argument("--frame-probe", action="store_true",
+                    help="only sample the d=49 measurement record 3 times (for profiling k_noise_gen and "
+                         "k_frame)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -446,6 +449,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
+
+    if args.frame_probe:
+        circ = stim_gpu.Circuit(workloads.surface_code(D, ROUNDS, P))
+        meas = torch.empty((circ.num_measurements, (SHOTS + 63) // 64), dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            stim_gpu.stim_frame_sample(circ.handle, SEED, 0, SHOTS, meas)
+        torch.cuda.synchronize()
+        print(json.dumps({"frame_probe": f"d={D}", "calls": 3}), flush=True)
         return
 
     if args.reference_probe is not None:
