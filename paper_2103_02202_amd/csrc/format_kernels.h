@@ -8,8 +8,9 @@
 namespace stimgpu {
 
 // Row stride (in uint64) of the shot-major scratch table T: ceil(rows / 64)
-// chunks rounded up to a multiple of four.
-inline uint64_t transpose_stride(uint64_t rows) { return ((rows + 63) / 64 + 3) / 4 * 4; }
+// chunks rounded up to a multiple of eight (the transpose writes 64-byte
+// pieces of each shot).
+inline uint64_t transpose_stride(uint64_t rows) { return ((rows + 63) / 64 + 7) / 8 * 8; }
 
 // table [rows][W] (bit j of word w = shot 64 w + j) -> T [shots][stride]
 // (bit i of T[s][c] = row 64 c + i of shot s; rows past the end read as 0).

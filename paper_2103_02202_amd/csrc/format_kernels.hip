@@ -14,6 +14,7 @@
 #include <cstdint>
 
 #include "format_kernels.h"
+#include "lds_attr.h"
 
 namespace stimgpu {
 
@@ -53,22 +54,29 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane) {
   return x;
 }
 
-// One workgroup (1024 threads) per block of 4 x 64 rows x 16 words:
-// coalesced 128-byte row segments into LDS, then each wave transposes the four
-// 64 x 64 blocks of one word column and writes each shot's four chunks as
-// 32 contiguous bytes (T rows are padded to a multiple of four chunks).
-// B8: instead of T, write the b8 bytes directly -- bytes [32 cg, 32 cg + 32)
+// One workgroup (1024 threads) per block of kTransposeChunks x 64 rows x 16
+// words: coalesced 128-byte row segments into LDS, then each wave transposes
+// the kTransposeChunks 64 x 64 blocks of one word column and writes each of
+// its 64 shots' chunks as one contiguous piece of 8 kTransposeChunks bytes
+// (T rows are padded to a multiple of kTransposeChunks chunks), so that a
+// shot's piece covers whole 64-byte lines.
+// B8: instead of T, write the b8 bytes directly -- bytes [64 cg, 64 cg + 64)
 // of shot s's row, clipped to its nbytes, at out + s nbytes (nbytes a
 // multiple of 4, so every piece starts on a 4-byte boundary; other widths go
 // through T and k_b8, since byte stores at unaligned piece ends cost more
 // than the second pass).
+constexpr uint32_t kTransposeChunks = 8;
+constexpr size_t kTransposeLds = (size_t)kTransposeChunks * 64 * 17 * sizeof(uint64_t);
+
 template <bool B8>
 __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__ table, uint64_t rows, uint64_t W,
                                                     uint64_t shots, uint32_t nchunks, uint32_t tstride,
                                                     uint64_t *__restrict__ T, uint8_t *__restrict__ out,
                                                     uint64_t nbytes) {
-  __shared__ uint64_t tile[256][17];
-  const uint32_t ngroups = (nchunks + 3) / 4;
+  constexpr uint32_t NB = kTransposeChunks;
+  extern __shared__ uint64_t tile_mem[];
+  uint64_t(*tile)[17] = reinterpret_cast<uint64_t(*)[17]>(tile_mem);    // [NB * 64][17]
+  const uint32_t ngroups = (nchunks + NB - 1) / NB;
   // Chunk-group-fastest order: workgroups on one XCD at the same time fill
   // neighbouring pieces of the same T rows.
   const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
@@ -78,40 +86,38 @@ __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__
     const uint32_t rr = threadIdx.x >> 4, ww = threadIdx.x & 15;
     const uint64_t w = w0 + ww;
 #pragma unroll
-    for (int h = 0; h < 4; h++) {
-      const uint64_t r = (uint64_t)cg * 256 + h * 64 + rr;
+    for (uint32_t h = 0; h < NB; h++) {
+      const uint64_t r = (uint64_t)cg * NB * 64 + h * 64 + rr;
       tile[h * 64 + rr][ww] = (r < rows && w < W) ? table[r * W + w] : 0;
     }
   }
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63, k = threadIdx.x >> 6;
   typedef uint64_t V2 __attribute__((ext_vector_type(2)));
-  V2 y0, y1;
-  y0.x = transpose64(tile[lane][k], lane);
-  y0.y = transpose64(tile[64 + lane][k], lane);
-  y1.x = transpose64(tile[128 + lane][k], lane);
-  y1.y = transpose64(tile[192 + lane][k], lane);
+  uint64_t y[NB];
+#pragma unroll
+  for (uint32_t h = 0; h < NB; h++) y[h] = transpose64(tile[h * 64 + lane][k], lane);
   const uint64_t s = (w0 + k) * 64 + lane;
   if (s < shots) {
     if constexpr (B8) {
       typedef uint32_t U32x4a __attribute__((ext_vector_type(4), aligned(4)));
-      const uint64_t b0 = (uint64_t)cg * 32;                    // < nbytes: group cg holds row bits
+      const uint64_t b0 = (uint64_t)cg * NB * 8;                 // < nbytes: group cg holds row bits
       uint8_t *row = out + s * nbytes + b0;
-      const uint32_t w[8] = {(uint32_t)y0.x, (uint32_t)(y0.x >> 32), (uint32_t)y0.y, (uint32_t)(y0.y >> 32),
-                             (uint32_t)y1.x, (uint32_t)(y1.x >> 32), (uint32_t)y1.y, (uint32_t)(y1.y >> 32)};
-      if (nbytes - b0 >= 32) {
-        reinterpret_cast<U32x4a *>(row)[0] = U32x4a{w[0], w[1], w[2], w[3]};
-        reinterpret_cast<U32x4a *>(row)[1] = U32x4a{w[4], w[5], w[6], w[7]};
+      if (nbytes - b0 >= NB * 8) {
+#pragma unroll
+        for (uint32_t h = 0; h < NB; h += 2)
+          reinterpret_cast<U32x4a *>(row)[h / 2] = U32x4a{(uint32_t)y[h], (uint32_t)(y[h] >> 32),
+                                                          (uint32_t)y[h + 1], (uint32_t)(y[h + 1] >> 32)};
       } else {
         const uint32_t nw = (uint32_t)(nbytes - b0) / 4;
 #pragma unroll
-        for (uint32_t i = 0; i < 8; i++)
-          if (i < nw) reinterpret_cast<uint32_t *>(row)[i] = w[i];
+        for (uint32_t i = 0; i < 2 * NB; i++)
+          if (i < nw) reinterpret_cast<uint32_t *>(row)[i] = (uint32_t)(y[i / 2] >> (32 * (i & 1)));
       }
     } else {
-      V2 *dst = reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * 4);
-      dst[0] = y0;
-      dst[1] = y1;
+      V2 *dst = reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * NB);
+#pragma unroll
+      for (uint32_t h = 0; h < NB; h += 2) dst[h / 2] = V2{y[h], y[h + 1]};
     }
   }
 }
@@ -148,42 +154,73 @@ __global__ void __launch_bounds__(256) k_b8(const uint64_t *__restrict__ T, uint
   }
 }
 
-// 01: one character per row and a newline per shot.  As for b8, a thread
-// writes one aligned 4-byte word of the output lying inside shot s's line
-// (built from four result bits), and the ragged ends are written singly.
+// 01: one character per row and a newline per shot.  A thread writes one
+// aligned 16-byte piece of the output lying inside shot s's line (sixteen
+// characters from sixteen result bits), and the ragged ends -- at most fifteen
+// bytes at each end of a line, which share a 16-byte piece with the
+// neighbouring line -- are written singly.
 __device__ __forceinline__ uint8_t char01(const uint64_t *row, uint64_t r, uint64_t rows) {
   return r < rows ? (uint8_t)('0' + ((row[r >> 6] >> (r & 63)) & 1)) : (uint8_t)'\n';
 }
 
+// Four result bits (bit k = character k) as four '0'/'1' bytes.
+__device__ __forceinline__ uint32_t chars4(uint32_t b) {
+  return 0x30303030u | (b & 1u) | (b & 2u) << 7 | (b & 4u) << 14 | (b & 8u) << 21;
+}
+
 __global__ void __launch_bounds__(256) k_01(const uint64_t *__restrict__ T, uint32_t tstride, uint64_t shots,
                                             uint64_t rows, uint8_t *__restrict__ out) {
+  // Pieces are 16-byte aligned relative to `out`, which is 4-byte aligned.
+  typedef uint32_t U32x4 __attribute__((ext_vector_type(4), aligned(4)));
+  constexpr int S = 4;                                 // shots per iteration: their loads go out together
   const uint64_t width = rows + 1;
   const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint64_t s = blockIdx.y; s < shots; s += gridDim.y) {
-    const uint64_t *row = T + s * tstride;
-    const uint64_t a0 = s * width, a1 = a0 + width;
-    const uint64_t first = (a0 + 3) / 4, last = a1 / 4;
-    const uint64_t ow = first + q;
-    if (ow < last) {
-      const uint64_t r = ow * 4 - a0;                  // first row of this word
-      uint32_t v;
-      if (r + 4 <= rows) {
-        const uint32_t sh = (uint32_t)(r & 63);
-        uint64_t bits = row[r >> 6] >> sh;
-        if (sh > 60) bits |= row[(r >> 6) + 1] << (64 - sh);
-        v = 0x30303030u | (uint32_t)(bits & 1) | (uint32_t)((bits >> 1) & 1) << 8 |
-            (uint32_t)((bits >> 2) & 1) << 16 | (uint32_t)((bits >> 3) & 1) << 24;
-      } else {
-        v = 0;
-        for (uint32_t k = 0; k < 4; k++) v |= (uint32_t)char01(row, r + k, rows) << (8 * k);
-      }
-      reinterpret_cast<uint32_t *>(out)[ow] = v;
+  for (uint64_t s0 = blockIdx.y; s0 < shots; s0 += (uint64_t)gridDim.y * S) {
+    uint64_t lo[S], hi[S];
+#pragma unroll
+    for (int i = 0; i < S; i++) {
+      const uint64_t s = s0 + (uint64_t)i * gridDim.y;
+      const uint64_t a0 = s * width;
+      const uint64_t r = ((a0 + 15) / 16 + q) * 16 - a0;
+      const bool full = s < shots && r + 16 <= rows;
+      const uint64_t *row = T + (full ? s : 0) * tstride;
+      const uint64_t c = full ? r >> 6 : 0;
+      lo[i] = row[c];
+      hi[i] = (full && (r & 63) > 48) ? row[c + 1] : 0;
     }
-    if (q < 4) {                                       // ragged ends of the line
-      const uint64_t head = first * 4 - a0 < width ? first * 4 - a0 : width;
-      if (q < head) out[a0 + q] = char01(row, q, rows);
-      const uint64_t tail_start = last * 4 > a0 + head ? last * 4 : a0 + head;
-      if (tail_start + q < a1) out[tail_start + q] = char01(row, tail_start + q - a0, rows);
+#pragma unroll
+    for (int i = 0; i < S; i++) {
+      const uint64_t s = s0 + (uint64_t)i * gridDim.y;
+      if (s >= shots) break;
+      const uint64_t *row = T + s * tstride;
+      const uint64_t a0 = s * width, a1 = a0 + width;
+      const uint64_t first = (a0 + 15) / 16, last = a1 / 16;     // whole 16-byte pieces [first, last)
+      const uint64_t ow = first + q;
+      if (ow < last) {
+        const uint64_t r = ow * 16 - a0;               // first row of this piece
+        U32x4 v;
+        if (r + 16 <= rows) {
+          const uint32_t sh = (uint32_t)(r & 63);
+          uint64_t bits = lo[i] >> sh;
+          if (sh > 48) bits |= hi[i] << (64 - sh);
+          v = U32x4{chars4((uint32_t)bits & 15u), chars4((uint32_t)(bits >> 4) & 15u),
+                    chars4((uint32_t)(bits >> 8) & 15u), chars4((uint32_t)(bits >> 12) & 15u)};
+        } else {                                       // the piece holding the newline
+          uint32_t w[4];
+          for (uint32_t j = 0; j < 4; j++) {
+            w[j] = 0;
+            for (uint32_t k = 0; k < 4; k++) w[j] |= (uint32_t)char01(row, r + 4 * j + k, rows) << (8 * k);
+          }
+          v = U32x4{w[0], w[1], w[2], w[3]};
+        }
+        reinterpret_cast<U32x4 *>(out)[ow] = v;
+      }
+      if (q < 16) {                                    // ragged ends of the line
+        const uint64_t head = first * 16 - a0 < width ? first * 16 - a0 : width;
+        if (q < head) out[a0 + q] = char01(row, q, rows);
+        const uint64_t tail_start = last * 16 > a0 + head ? last * 16 : a0 + head;
+        if (tail_start + q < a1) out[tail_start + q] = char01(row, tail_start + q - a0, rows);
+      }
     }
   }
 }
@@ -365,31 +402,36 @@ __global__ void __launch_bounds__(256) k_scan_apply(const uint64_t *__restrict__
 
 hipError_t launch_transpose(const uint64_t *table, uint64_t rows, uint64_t W, uint64_t shots, uint64_t *T,
                             hipStream_t stream) {
-  const uint64_t nchunks = (rows + 63) / 64, ngroups = (nchunks + 3) / 4, wblocks = (W + 15) / 16;
-  const uint64_t blocks = ngroups * wblocks;
+  const uint64_t nchunks = (rows + 63) / 64, ngroups = (nchunks + kTransposeChunks - 1) / kTransposeChunks;
+  const uint64_t wblocks = (W + 15) / 16, blocks = ngroups * wblocks;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFull || nchunks > 0x3FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_transpose<false>, dim3((uint32_t)blocks), dim3(1024), 0, stream, table, rows, W, shots,
-                     (uint32_t)nchunks, (uint32_t)transpose_stride(rows), T, (uint8_t *)nullptr, (uint64_t)0);
+  hipError_t e = allow_dynamic_lds((const void *)k_transpose<false>, (int)kTransposeLds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose<false>, dim3((uint32_t)blocks), dim3(1024), kTransposeLds, stream, table, rows, W,
+                     shots, (uint32_t)nchunks, (uint32_t)transpose_stride(rows), T, (uint8_t *)nullptr, (uint64_t)0);
   return hipGetLastError();
 }
 
 hipError_t launch_transpose_b8(const uint64_t *table, uint64_t rows, uint64_t W, uint64_t shots, uint8_t *out,
                                hipStream_t stream) {
-  const uint64_t nchunks = (rows + 63) / 64, ngroups = (nchunks + 3) / 4, wblocks = (W + 15) / 16;
-  const uint64_t blocks = ngroups * wblocks, nbytes = (rows + 7) / 8;
+  const uint64_t nchunks = (rows + 63) / 64, ngroups = (nchunks + kTransposeChunks - 1) / kTransposeChunks;
+  const uint64_t wblocks = (W + 15) / 16, blocks = ngroups * wblocks, nbytes = (rows + 7) / 8;
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7FFFFFFFull || nchunks > 0x3FFFFFFFull || nbytes % 4 || (uintptr_t)out % 4)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_transpose<true>, dim3((uint32_t)blocks), dim3(1024), 0, stream, table, rows, W, shots,
-                     (uint32_t)nchunks, (uint32_t)transpose_stride(rows), (uint64_t *)nullptr, out, nbytes);
+  hipError_t e = allow_dynamic_lds((const void *)k_transpose<true>, (int)kTransposeLds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose<true>, dim3((uint32_t)blocks), dim3(1024), kTransposeLds, stream, table, rows, W,
+                     shots, (uint32_t)nchunks, (uint32_t)transpose_stride(rows), (uint64_t *)nullptr, out, nbytes);
   return hipGetLastError();
 }
 
 hipError_t launch_dense_format(const uint64_t *T, uint64_t rows, uint64_t shots, int b8, uint8_t *out,
                                hipStream_t stream) {
   const uint64_t width = b8 ? (rows + 7) / 8 : rows + 1;
-  const uint64_t xb = (width / 4 + 1 + 255) / 256;
+  const uint64_t piece = b8 ? 4 : 16;                  // bytes per thread and store
+  const uint64_t xb = (width / piece + 1 + 255) / 256;
   if (shots == 0) return hipSuccess;
   if (xb > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const uint32_t tstride = (uint32_t)transpose_stride(rows);
