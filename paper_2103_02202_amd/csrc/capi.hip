@@ -755,8 +755,12 @@ void load_tune_cache() {
   int T = 0;
   unsigned threads = 0;
   while (std::fscanf(f, "%127s %d %u", cls, &T, &threads) == 3) {
-    if ((T == 1 || T == 2 || T == 4 || T == 8) && threads >= 64 && threads <= 1024 && threads % 64 == 0)
-      g_tuned[cls] = FrameConfig{T, true, threads};
+    // 64 threads names the one-wave-per-tile kernel.
+    if ((T == 1 || T == 2 || T == 4 || T == 8) && threads >= 64 && threads <= 1024 && threads % 64 == 0) {
+      FrameConfig cfg{T, true, threads};
+      cfg.wave = threads == 64;
+      g_tuned[cls] = cfg;
+    }
   }
   std::fclose(f);
 }
@@ -766,7 +770,7 @@ void save_tuned(const std::string &cls, const FrameConfig &cfg) {
   const char *path = std::getenv("STIM_TUNE_CACHE");
   if (!path || !*path) return;
   if (FILE *f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s %d %u\n", cls.c_str(), cfg.tile_words, cfg.threads);
+    std::fprintf(f, "%s %d %u\n", cls.c_str(), cfg.tile_words, cfg.wave ? 64u : cfg.threads);
     std::fclose(f);
   }
 }
@@ -858,13 +862,23 @@ bool batch_fits(uint64_t n, int T, uint32_t threads) {
   return frame_lds_bytes(n, T, true, threads) + kBatchStaticLds <= kMaxLdsBytes;
 }
 
+// Whether a configuration can run a request set whose largest circuit has n
+// qubits: a workgroup tile in LDS, or (one wave per tile) at least four waves'
+// tiles per workgroup.
+bool config_fits(uint64_t n, const FrameConfig &cfg) {
+  return cfg.wave ? batch_waves_per_block(n, cfg.tile_words) >= 4 : batch_fits(n, cfg.tile_words, cfg.threads);
+}
+
 // The tuned configuration of a plan's shape class, if there is one that fits
 // this plan: a class spans a factor of two in qubit count, so a width tuned
 // for its smaller circuits may not fit the LDS of its larger ones.
 std::string shape_class(const BatchPlan &pl);
+int batch_wave_mode();
 bool tuned_config(const BatchPlan &pl, FrameConfig *cfg) {
   auto known = g_tuned.find(shape_class(pl));
-  if (known == g_tuned.end() || !batch_fits(pl.max_n, known->second.tile_words, known->second.threads)) return false;
+  if (known == g_tuned.end() || !config_fits(pl.max_n, known->second)) return false;
+  const int wave_mode = batch_wave_mode();
+  if (wave_mode >= 0 && known->second.wave != (wave_mode == 1)) return false;
   *cfg = known->second;
   return true;
 }
@@ -1006,7 +1020,21 @@ std::vector<BatchItem> work_list(const BatchPlan &pl, int T) {
   return items;
 }
 
+// STIM_BATCH_WAVE = 1 / 0 forces the one-wave-per-tile kernel / the
+// workgroup kernel for batched launches (default: the tuner chooses).
+int batch_wave_mode() {
+  const char *v = std::getenv("STIM_BATCH_WAVE");
+  return v ? (std::atoi(v) ? 1 : 0) : -1;
+}
+
 FrameConfig untuned_batch_config(uint64_t max_n) {
+  if (batch_wave_mode() == 1) {
+    for (int T : {2, 1}) {
+      FrameConfig w{T, true, 64};
+      w.wave = true;
+      if (config_fits(max_n, w)) return w;
+    }
+  }
   for (int T : {4, 2, 1})
     if (batch_fits(max_n, T, 256)) return FrameConfig{T, true, 256};
   return FrameConfig{1, true, 256};
@@ -1059,9 +1087,16 @@ int build_plan(BatchPlan &pl, hipStream_t s) {
 
   // Candidate configurations; the work list depends on the tile width.
   std::vector<FrameConfig> cands;
-  for (int T : {1, 2, 4, 8})
-    for (uint32_t th : {256u, 512u, 1024u})
-      if (batch_fits(pl.max_n, T, th)) cands.push_back(FrameConfig{T, true, th});
+  const int wave_mode = batch_wave_mode();
+  for (int T : {1, 2, 4, 8}) {
+    if (wave_mode != 1)
+      for (uint32_t th : {256u, 512u, 1024u})
+        if (batch_fits(pl.max_n, T, th)) cands.push_back(FrameConfig{T, true, th});
+    FrameConfig w{T, true, 64};
+    w.wave = true;
+    if (wave_mode != 0 && config_fits(pl.max_n, w)) cands.push_back(w);
+  }
+  if (cands.empty()) cands.push_back(untuned_batch_config(pl.max_n));
   const char *tune_env = std::getenv("STIM_TUNE");
   const bool tune = !(tune_env && std::strcmp(tune_env, "0") == 0);
   const std::string cls = shape_class(pl);

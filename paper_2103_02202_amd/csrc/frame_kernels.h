@@ -66,6 +66,7 @@ struct FrameConfig {
   bool in_lds;
   uint32_t threads;
   uint32_t slots = 0;           // global frame: workgroups (and scratch slots); 0 = one per tile
+  bool wave = false;            // batched launches: one wave per tile (k_batch_wave)
 };
 
 // LDS available to one workgroup on gfx950.
@@ -95,6 +96,11 @@ hipError_t launch_batch(const FrameParams *reqs, const BatchItem *items, uint32_
                         const FrameConfig &cfg, uint64_t max_qubits, uint32_t blocks, hipStream_t stream);
 // Workgroups of the batch kernel that fit on one CU at once.
 int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits);
+// One-wave-per-tile batches: LDS of one wave's tile (queue, threshold row,
+// frame slice of n + 1 rows), and the waves of one workgroup (at most 16; 0
+// when one wave's tile does not fit).
+size_t wave_lds_bytes(uint64_t n, int T);
+uint32_t batch_waves_per_block(uint64_t n, int T);
 // Detection events / observable flips: row r of `out` = XOR of the flip rows
 // idx[off[r] .. off[r+1]).  Rows are visited in `order` (NULL: 0, 1, ...).
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,

@@ -61,6 +61,29 @@ __device__ __forceinline__ void tile_barrier() {
   }
 }
 
+// The threads that walk one tile: the whole workgroup, or (WAVE) one wave of
+// it that walks its own tile with wave-level synchronisation only.
+template <bool WAVE>
+__device__ __forceinline__ uint32_t team_tid() { return WAVE ? (threadIdx.x & 63u) : threadIdx.x; }
+template <bool WAVE>
+__device__ __forceinline__ uint32_t team_size() { return WAVE ? 64u : blockDim.x; }
+template <bool IN_LDS, bool WAVE>
+__device__ __forceinline__ void team_barrier() {
+  if constexpr (WAVE) wave_sync();
+  else tile_barrier<IN_LDS>();
+}
+// Barrier over all memory: the team then reads global words it wrote.
+template <bool WAVE>
+__device__ __forceinline__ void team_barrier_all() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Exclusive prefix sum over the 64 lanes of a wave; *total gets the sum.
 __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t lane, uint32_t *total) {
   uint32_t x = v;
@@ -110,11 +133,11 @@ struct PhiloxCall {
 
 // Applies a noise op: prefix test per (32-slot group, word), wave-compacted
 // expansion of the surviving (slot, word) pairs.
-template <int T, bool IN_LDS>
+template <int T, bool IN_LDS, bool WAVE>
 __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                       uint32_t code, uint64_t instr, const uint64_t *thr) {
   const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t lane = threadIdx.x & 63, wave = WAVE ? 0u : threadIdx.x >> 6, nwaves = WAVE ? 1u : blockDim.x >> 6;
   const uint64_t cut = thr[63] >> 56;            // prefix below cut: no error in the word
   // 1 / log2(1 - p) from the exact value 2^64 - t[0] ~ p 2^64; seeds the gap search.
   const float p_est = (float)(0ull - thr[0]) * 0x1p-64f + (thr[0] == 0 ? 1.0f : 0.0f);
@@ -186,7 +209,7 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
 // Every thread runs at least one pass, and every load of a pass is issued
 // unconditionally (clamped indices), then `after_loads` runs: loads complete in issue order, so the loads it
 // issues stay in flight while the pass waits only for its own.
-template <int T, bool IN_LDS, typename AfterLoads>
+template <int T, bool IN_LDS, bool WAVE, typename AfterLoads>
 __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                             uint32_t code, uint64_t instr, uint64_t meas, AfterLoads after_loads) {
   constexpr int V = 2;
@@ -197,8 +220,8 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
   const bool measures = code == OP_M || code == OP_MR;
   const bool use_ref = measures && p.ref != nullptr;
   const bool all_live = (op.code & OPF_ZRAND_LIVE) != 0;       // uniform
-  const uint32_t stride = blockDim.x;
-  uint32_t base = threadIdx.x;
+  const uint32_t stride = team_size<WAVE>();
+  uint32_t base = team_tid<WAVE>();
   do {
     uint32_t tv[V][4];
     bool ok[V];
@@ -283,7 +306,7 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
 // are updated too (they belong to no shot and are never written out).  Every
 // thread runs at least one pass; loads use clamped indices, so they are issued
 // on every path and the compiler waits only for the loads it needs.
-template <int T, bool IN_LDS, uint32_t CODE, typename AfterLoads>
+template <int T, bool IN_LDS, bool WAVE, uint32_t CODE, typename AfterLoads>
 __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                             AfterLoads after_loads) {
   constexpr int U = 3;
@@ -295,17 +318,18 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
   typedef typename Tile<T, IN_LDS>::Index Index;
   const uint32_t items = op.n * CPT;
   const uint32_t *tg = p.targets + op.toff;
-  const uint32_t per_pass = U * blockDim.x;
+  const uint32_t tsize = team_size<WAVE>();
+  const uint32_t per_pass = U * tsize;
   const uint32_t passes = items > per_pass ? (items + per_pass - 1) / per_pass : 1u;     // uniform
   auto X = [&](Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FX + i); };
   auto Z = [&](Index i) -> Vec & { return *reinterpret_cast<Vec *>(tl.FZ + i); };
   for (uint32_t pass = 0; pass < passes; pass++) {
-    const uint32_t base = threadIdx.x + pass * per_pass;
+    const uint32_t base = team_tid<WAVE>() + pass * per_pass;
     uint32_t qa[U], qb[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const uint32_t it = base + u * blockDim.x;
+      const uint32_t it = base + u * tsize;
       ok[u] = it < items;
       const uint32_t k = ok[u] ? it / CPT : 0u;
       if constexpr (TWO) {
@@ -324,7 +348,7 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
     Vec xa[U], za[U], xb[U], zb[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const int j = (int)(((base + u * blockDim.x) % CPT) * C);
+      const int j = (int)(((base + u * tsize) % CPT) * C);
       ra[u] = tl.at(qa[u], j);
       rb[u] = tl.at(qb[u], j);
       wa[u] = ok[u] ? ra[u] : tl.at(tl.dummy, j);
@@ -376,13 +400,13 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
 // acted on the qubit since) takes the difference from the qubit's own frame
 // x bit instead: no barrier over memory and no load; an op whose pairs are
 // all local needs neither.
-template <int T, bool IN_LDS>
+template <int T, bool IN_LDS, bool WAVE>
 __device__ __forceinline__ void feedback_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                             uint32_t code, uint64_t meas) {
-  if (!(op.code & OPF_FB_LOCAL)) __syncthreads();
+  if (!(op.code & OPF_FB_LOCAL)) team_barrier_all<WAVE>();
   const uint32_t items = op.n * T;
   const uint32_t *tg = p.targets + op.toff;
-  for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+  for (uint32_t it = team_tid<WAVE>(); it < items; it += team_size<WAVE>()) {
     const uint32_t k = it / T;
     const int j = (int)(it % T);
     if (j >= tl.valid) continue;
@@ -436,18 +460,19 @@ __device__ __forceinline__ void apply_record(const Tile<T, IN_LDS> &tl, uint32_t
 
 // Records of one noise execution for this tile; the first two per thread may
 // already be in registers (loaded one op earlier).
-template <int T, bool IN_LDS>
+template <int T, bool IN_LDS, bool WAVE>
 __device__ __forceinline__ void apply_records(const Tile<T, IN_LDS> &tl, uint32_t code, const uint4 *rec,
                                               uint32_t count, bool have, const uint4 &r0, const uint4 &r1) {
   const int K = code == OP_NOISE_DEP1 ? 3 : code == OP_NOISE_DEP2 ? 15 : 0;
-  uint32_t e = threadIdx.x;
+  const uint32_t tsize = team_size<WAVE>();
+  uint32_t e = team_tid<WAVE>();
   if (have) {
     if (e < count) apply_record(tl, code, K, r0);
-    e += blockDim.x;
+    e += tsize;
     if (e < count) apply_record(tl, code, K, r1);
-    e += blockDim.x;
+    e += tsize;
   }
-  for (; e < count; e += blockDim.x) apply_record(tl, code, K, rec[e]);
+  for (; e < count; e += tsize) apply_record(tl, code, K, rec[e]);
 }
 
 // Noise pre-pass: one workgroup per (noise execution, group of up to
@@ -606,12 +631,12 @@ __device__ __forceinline__ uint2 load_meta(const uint32_t *w) {
 
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
 // LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
-template <int T, bool IN_LDS>
+template <int T, bool IN_LDS, bool WAVE = false>
 __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, uint32_t slot, uint64_t *lds) {
-  const uint32_t nwaves = blockDim.x >> 6;
+  const uint32_t nwaves = WAVE ? 1u : blockDim.x >> 6;
   const uint32_t n = p.num_qubits;
   Tile<T, IN_LDS> tl;
-  tl.queue = lds + (threadIdx.x >> 6) * 64;
+  tl.queue = lds + (WAVE ? 0u : (threadIdx.x >> 6) * 64);
   uint64_t *thr_lds = lds + nwaves * 64;         // threshold row of the current noise op
   uint32_t thr_row = 0xFFFFFFFFu;
   uint64_t *F;
@@ -658,8 +683,8 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     pf_count = ok ? count : kNoRecords;
     pf_rec = p.noise_rec + (ok ? first : 0u);
     const auto rs = buffer_rsrc(pf_rec, ok ? count * 16u : 0u);
-    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, threadIdx.x * 16u, 0, 0);
-    const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (threadIdx.x + blockDim.x) * 16u, 0, 0);
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, team_tid<WAVE>() * 16u, 0, 0);
+    const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (team_tid<WAVE>() + team_size<WAVE>()) * 16u, 0, 0);
     pf_r0 = make_uint4(v0[0], v0[1], v0[2], v0[3]);
     pf_r1 = make_uint4(v1[0], v1[1], v1[2], v1[3]);
   };
@@ -689,7 +714,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       instr = flat - 1;
     }
     if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
-      collapse_op<T, IN_LDS>(p, tl, op, code, instr, meas, stage_b);
+      collapse_op<T, IN_LDS, WAVE>(p, tl, op, code, instr, meas, stage_b);
     } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
       const uint32_t inst = noise_seq++;
       uint32_t count = kNoRecords;                 // same value in every thread
@@ -706,30 +731,31 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       pf_inst = 0xFFFFFFFFu;
       stage_a(inst + 1);
       if (count != kNoRecords) {
-        apply_records<T, IN_LDS>(tl, code, rec, count, have, pf_r0, pf_r1);
+        apply_records<T, IN_LDS, WAVE>(tl, code, rec, count, have, pf_r0, pf_r1);
       } else {
         if (op.aux != thr_row) {
           thr_row = op.aux;
-          if (threadIdx.x < 64) thr_lds[threadIdx.x] = p.thresholds[(size_t)thr_row * 64 + threadIdx.x];
-          tile_barrier<IN_LDS>();
+          const uint32_t tt = team_tid<WAVE>();
+          if (tt < 64) thr_lds[tt] = p.thresholds[(size_t)thr_row * 64 + tt];
+          team_barrier<IN_LDS, WAVE>();
         }
-        noise_op<T, IN_LDS>(p, tl, op, code, instr, thr_lds);
+        noise_op<T, IN_LDS, WAVE>(p, tl, op, code, instr, thr_lds);
       }
     } else if (code >= OP_FB_X) {
-      feedback_op<T, IN_LDS>(p, tl, op, code, meas);
+      feedback_op<T, IN_LDS, WAVE>(p, tl, op, code, meas);
     } else {
       switch (code) {
-        case OP_SWAP_XZ: clifford_op<T, IN_LDS, OP_SWAP_XZ>(p, tl, op, stage_b); break;
-        case OP_Z_XOR_X: clifford_op<T, IN_LDS, OP_Z_XOR_X>(p, tl, op, stage_b); break;
-        case OP_X_XOR_Z: clifford_op<T, IN_LDS, OP_X_XOR_Z>(p, tl, op, stage_b); break;
-        case OP_CX: clifford_op<T, IN_LDS, OP_CX>(p, tl, op, stage_b); break;
-        case OP_CY: clifford_op<T, IN_LDS, OP_CY>(p, tl, op, stage_b); break;
-        case OP_CZ: clifford_op<T, IN_LDS, OP_CZ>(p, tl, op, stage_b); break;
-        default: clifford_op<T, IN_LDS, OP_SWAP>(p, tl, op, stage_b); break;
+        case OP_SWAP_XZ: clifford_op<T, IN_LDS, WAVE, OP_SWAP_XZ>(p, tl, op, stage_b); break;
+        case OP_Z_XOR_X: clifford_op<T, IN_LDS, WAVE, OP_Z_XOR_X>(p, tl, op, stage_b); break;
+        case OP_X_XOR_Z: clifford_op<T, IN_LDS, WAVE, OP_X_XOR_Z>(p, tl, op, stage_b); break;
+        case OP_CX: clifford_op<T, IN_LDS, WAVE, OP_CX>(p, tl, op, stage_b); break;
+        case OP_CY: clifford_op<T, IN_LDS, WAVE, OP_CY>(p, tl, op, stage_b); break;
+        case OP_CZ: clifford_op<T, IN_LDS, WAVE, OP_CZ>(p, tl, op, stage_b); break;
+        default: clifford_op<T, IN_LDS, WAVE, OP_SWAP>(p, tl, op, stage_b); break;
       }
     }
     if (code == OP_M || code == OP_MR) meas += op.n;
-    tile_barrier<IN_LDS>();
+    team_barrier<IN_LDS, WAVE>();
   }
 }
 
@@ -782,6 +808,43 @@ __global__ void __launch_bounds__(1024) k_batch(const FrameParams *__restrict__ 
       __builtin_memcpy(&p, w, sizeof p);
     }
     walk_tile<T, true>(p, bi.tile, 0, lds);
+  }
+}
+
+// The same persistent walk with one wave per tile: each wave pops (request,
+// tile) items on its own and walks them in its own LDS region (queue,
+// threshold row, frame slice of `wave_words` words in all), synchronising with
+// wave barriers only.  For small circuits, whose ops have few items, this
+// keeps many tiles in flight per CU instead of idling most of a workgroup.
+template <int T>
+__global__ void __launch_bounds__(1024) k_batch_wave(const FrameParams *__restrict__ reqs,
+                                                     const BatchItem *__restrict__ items, uint32_t num_items,
+                                                     uint32_t *counter, uint32_t wave_words) {
+  extern __shared__ uint64_t lds[];
+  uint64_t *mine = lds + (size_t)(threadIdx.x >> 6) * wave_words;
+  while (true) {
+    uint32_t it = 0;
+    if ((threadIdx.x & 63) == 0) it = atomicAdd(counter, 1u);
+    it = __builtin_amdgcn_readfirstlane(it);       // lane 0's item for the whole wave
+    if (it >= num_items) break;                    // uniform within the wave
+    typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+    BatchItem bi;
+    {
+      ConstU32 *src = (ConstU32 *)(items + it);
+      uint32_t w[sizeof(BatchItem) / 4];
+#pragma unroll
+      for (size_t k = 0; k < sizeof(BatchItem) / 4; k++) w[k] = src[k];
+      __builtin_memcpy(&bi, w, sizeof bi);
+    }
+    FrameParams p;
+    {
+      ConstU32 *src = (ConstU32 *)(reqs + bi.req);
+      uint32_t w[sizeof(FrameParams) / 4];
+#pragma unroll
+      for (size_t k = 0; k < sizeof(FrameParams) / 4; k++) w[k] = src[k];
+      __builtin_memcpy(&p, w, sizeof p);
+    }
+    walk_tile<T, true, true>(p, bi.tile, 0, mine);
   }
 }
 
@@ -876,8 +939,40 @@ static hipError_t launch_batch_t(const FrameParams *reqs, const BatchItem *items
   return hipGetLastError();
 }
 
+size_t wave_lds_bytes(uint64_t n, int T) { return ((size_t)64 + 64) * sizeof(uint64_t) + (size_t)16 * (n + 1) * T; }
+
+uint32_t batch_waves_per_block(uint64_t n, int T) {
+  const size_t per = wave_lds_bytes(n, T);
+  const size_t w = per > kMaxLdsBytes ? 0 : kMaxLdsBytes / per;
+  return (uint32_t)(w < 16 ? w : 16);
+}
+
+template <int T>
+static hipError_t launch_batch_wave_t(const FrameParams *reqs, const BatchItem *items, uint32_t num_items,
+                                      uint32_t *counter, uint32_t blocks, uint32_t waves, uint64_t n,
+                                      hipStream_t stream) {
+  hipError_t e = allow_dynamic_lds((const void *)k_batch_wave<T>, (int)kMaxLdsBytes);
+  if (e != hipSuccess) return e;
+  const uint32_t words = (uint32_t)(wave_lds_bytes(n, T) / sizeof(uint64_t));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, stream, counter, 0u);
+  hipLaunchKernelGGL((k_batch_wave<T>), dim3(blocks), dim3(64 * waves), (size_t)waves * words * sizeof(uint64_t),
+                     stream, reqs, items, num_items, counter, words);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch(const FrameParams *reqs, const BatchItem *items, uint32_t num_items, uint32_t *counter,
                         const FrameConfig &cfg, uint64_t max_qubits, uint32_t blocks, hipStream_t stream) {
+  if (cfg.wave) {
+    const uint32_t waves = batch_waves_per_block(max_qubits, cfg.tile_words);
+    if (waves == 0 || wave_lds_bytes(max_qubits, cfg.tile_words) % 16) return hipErrorInvalidValue;
+    switch (cfg.tile_words) {
+      case 1: return launch_batch_wave_t<1>(reqs, items, num_items, counter, blocks, waves, max_qubits, stream);
+      case 2: return launch_batch_wave_t<2>(reqs, items, num_items, counter, blocks, waves, max_qubits, stream);
+      case 4: return launch_batch_wave_t<4>(reqs, items, num_items, counter, blocks, waves, max_qubits, stream);
+      case 8: return launch_batch_wave_t<8>(reqs, items, num_items, counter, blocks, waves, max_qubits, stream);
+      default: return hipErrorInvalidValue;
+    }
+  }
   size_t lds = frame_lds_bytes(max_qubits, cfg.tile_words, true, cfg.threads);
   if (lds + kBatchStaticLds > kMaxLdsBytes || cfg.threads % 64 || cfg.threads == 0 || cfg.threads > 1024)
     return hipErrorInvalidValue;
@@ -891,6 +986,7 @@ hipError_t launch_batch(const FrameParams *reqs, const BatchItem *items, uint32_
 }
 
 int batch_blocks_per_cu(const FrameConfig &cfg, uint64_t max_qubits) {
+  if (cfg.wave) return 1;                  // one block of up to 16 waves fills the LDS
   size_t lds = frame_lds_bytes(max_qubits, cfg.tile_words, true, cfg.threads) + kBatchStaticLds;
   int by_lds = (int)(kMaxLdsBytes / lds);
   int by_threads = 2048 / (int)cfg.threads;

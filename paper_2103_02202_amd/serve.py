@@ -302,11 +302,30 @@ class Server:
         stats["makespan_s"] = time.perf_counter() - t0
         return self._summary(reqs, stats)
 
+    # Requests below this many shot-gates count as small in the latency split.
+    SMALL_WORK = 1e10
+
     def _summary(self, reqs, stats):
-        sg = sum(self.pool[r["circuit"]].c.num_gate_targets * r["shots"] for r in reqs)
-        lat = stats["latencies"]
+        """Throughput and latency of one served stream.  Rates are equivalent
+        shot-gates per second (gate targets x shots of the requests over the
+        makespan): circuits served by sparse detection sampling produce the
+        same events without walking the gates.  Latencies are also split
+        between small requests (under SMALL_WORK shot-gates) and the rest."""
+        work = {id(r): self.pool[r["circuit"]].c.num_gate_targets * r["shots"] for r in reqs}
+        sg = sum(work.values())
+        lat = [r["completion"] - r["arrival"] for r in reqs if "completion" in r]
+        small = [r["completion"] - r["arrival"] for r in reqs if "completion" in r and work[id(r)] < self.SMALL_WORK]
+        large = [r["completion"] - r["arrival"] for r in reqs if "completion" in r and work[id(r)] >= self.SMALL_WORK]
+        frame_sg = sum(work[id(r)] for r in reqs if self.pool[r["circuit"]].method == "frame")
         return {"requests": len(reqs), "shot_gates": sg, "makespan_s": stats["makespan_s"],
-                "shot_gates_per_s": sg / stats["makespan_s"], "requests_per_s": len(reqs) / stats["makespan_s"],
+                "equivalent_shot_gates_per_s": sg / stats["makespan_s"],
+                "frame_path_shot_gates": frame_sg,
+                "requests_per_s": len(reqs) / stats["makespan_s"],
                 "p50_latency_ms": 1e3 * percentile(lat, 50), "p99_latency_ms": 1e3 * percentile(lat, 99),
-                "mean_latency_ms": 1e3 * sum(lat) / max(len(lat), 1), "deferrals": stats["deferrals"],
+                "mean_latency_ms": 1e3 * sum(lat) / max(len(lat), 1),
+                "small_requests": len(small), "small_p50_latency_ms": 1e3 * percentile(small, 50),
+                "small_p99_latency_ms": 1e3 * percentile(small, 99),
+                "large_p50_latency_ms": 1e3 * percentile(large, 50),
+                "large_p99_latency_ms": 1e3 * percentile(large, 99),
+                "deferrals": stats["deferrals"],
                 "launches": stats["launches"], "chunks": stats["chunks"], "max_group": stats["max_group"]}

@@ -235,10 +235,36 @@ def test_tuning_cache_file_round_trip(sg, tmp_path, monkeypatch):
     lines = cache.read_text().splitlines()
     assert len(lines) == 1
     cls, T, threads = lines[0].split()
-    assert int(T) in (1, 2, 4, 8) and int(threads) in (256, 512, 1024)
+    assert int(T) in (1, 2, 4, 8) and int(threads) in (64, 256, 512, 1024)      # 64: one wave per tile
     reqs2, circs2 = make_requests(sg, specs)         # same class, new outputs: a new plan
     for _ in range(2):
         sg.stim_batch_sample(reqs2)
         torch.cuda.synchronize()
     check_against_single(sg, reqs2, circs2)
     assert cache.read_text().splitlines() == lines
+
+
+@pytest.mark.parametrize("tune", ["0", "1"])
+def test_one_wave_per_tile_batches(sg, tune, monkeypatch):
+    """The batched walk with one wave per tile (STIM_BATCH_WAVE=1 forces it;
+    otherwise the tuner may pick it): noisy surface codes up to d=25, random
+    circuits, feedback and the repetition code, equal to their single calls on
+    the first submission, the captured one and a replay, and to the oracle."""
+    announce("one wave per tile", tune)
+    monkeypatch.setenv("STIM_BATCH_WAVE", "1")
+    monkeypatch.setenv("STIM_TUNE", tune)
+    specs = SPECS + [(wl.surface_code(5, 5, 1e-2, feedback_reset=True), 3000, 11, 1, 0),
+                     (random_circuit(12, 120, seed=91, noise=True, p=0.05, feedback=0.2), 2222, 12, 0, 64)]
+    reqs, circs = make_requests(sg, specs)
+    for _ in range(3):
+        for r in reqs:
+            r["out0"].fill_(-1)
+            if r["out1"] is not None:
+                r["out1"].fill_(-1)
+        sg.stim_batch_sample(reqs)
+        torch.cuda.synchronize()
+        check_against_single(sg, reqs, circs)
+    for (text, shots, seed, mode, offset), r in list(zip(specs, reqs))[:6]:
+        o = oracle.Circuit(text)
+        want = o.sample(seed, offset, shots, meas=mode == 0, det=mode == 1, obs=mode == 1)
+        assert np.array_equal(r["out0"].cpu().numpy().view(np.uint64), want["meas" if mode == 0 else "det"])
