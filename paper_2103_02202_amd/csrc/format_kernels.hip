@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "bit_transpose.h"
 #include "format_kernels.h"
 #include "lds_attr.h"
 
@@ -27,31 +28,6 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
   const uint32_t xcd = bid % X, local = bid / X;
   const uint32_t per = nblocks / X, rem = nblocks % X;
   return xcd * per + (xcd < rem ? xcd : rem) + local;
-}
-
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Transposes a 64 x 64 bit block held one row per lane: on entry lane l holds
-// row l (bit s = column s); on exit lane s holds column s (bit l = row l).
-// Recursive exchange of off-diagonal blocks of halving size.
-__device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane) {
-  uint64_t m = 0x00000000FFFFFFFFull;
-#pragma unroll
-  for (int j = 32; j != 0; j >>= 1) {
-    const uint64_t other = shfl_xor64(x, j);
-    if ((lane & j) == 0) {
-      const uint64_t t = ((x >> j) ^ other) & m;
-      x ^= t << j;
-    } else {
-      const uint64_t t = ((other >> j) ^ x) & m;
-      x ^= t;
-    }
-    m ^= m << (j >> 1);
-  }
-  return x;
 }
 
 // One workgroup (1024 threads) per block of kTransposeChunks x 64 rows x 16
@@ -96,7 +72,7 @@ __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__
   typedef uint64_t V2 __attribute__((ext_vector_type(2)));
   uint64_t y[NB];
 #pragma unroll
-  for (uint32_t h = 0; h < NB; h++) y[h] = transpose64(tile[h * 64 + lane][k], lane);
+  for (uint32_t h = 0; h < NB; h++) y[h] = bit_transpose64(tile[h * 64 + lane][k], lane);
   const uint64_t s = (w0 + k) * 64 + lane;
   if (s < shots) {
     if constexpr (B8) {

@@ -34,6 +34,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "bit_transpose.h"
 #include "circuit.h"
 #include "format_kernels.h"
 #include "reference_gpu.h"
@@ -177,12 +178,15 @@ constexpr uint32_t kRefThreads = 1024;
 constexpr uint32_t kRefList = 8192;          // support rows gathered per round
 
 // The ordered pass over a measurement step's random targets, one workgroup,
-// on the transposed tableau: XR[j] / ZR[j] hold, for qubit j, the x / z bit
-// of every column (stride s2 words), and SB the column signs.  Appending a
-// gate at the start of time is then a few word-parallel row operations
-// (the reason the paper transposes for bursts of random measurements).
+// on the transposed tableau: XR[cw * n + j] / ZR[cw * n + j] hold, for qubit
+// j, the x / z bits of columns 64 cw .. 64 cw + 63, and SB the column signs.
+// Appending a gate at the start of time is then a few word-parallel row
+// operations (the reason the paper transposes for bursts of random
+// measurements).  Words of one column group are contiguous over the qubits,
+// so the scan of a column for its pivot and support reads consecutive words;
+// a row operation touches one word per column group.
 __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR, uint64_t *ZR, uint64_t *SB,
-                                                                    uint32_t n, uint32_t s2, Gate gate,
+                                                                    uint32_t n, Gate gate,
                                                                     const uint32_t *tg, uint32_t count, uint64_t meas0,
                                                                     uint64_t *ref, const uint32_t *flag) {
   __shared__ uint32_t list[kRefList];
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR,
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const uint32_t j = j0 + u * blockDim.x;
-        v[u] = j < n ? XR[(size_t)j * s2 + cw] : 0;
+        v[u] = j < n ? XR[(size_t)cw * n + j] : 0;
       }
 #pragma unroll
       for (int u = 0; u < 4; u++) {
@@ -235,7 +239,8 @@ __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR,
       __syncthreads();
       continue;
     }
-    uint64_t *xp_row = XR + (size_t)p * s2, *zp_row = ZR + (size_t)p * s2;
+    // Word w of the pivot row: xp_row[w * n] (the row's words are n apart).
+    uint64_t *xp_row = XR + p, *zp_row = ZR + p;
     // CNOT appends from the pivot onto every other row with an X/Y term in
     // column c (the pivot's own entry in the list is skipped).  A support
     // larger than the list is handled in rounds: an append clears the row's
@@ -249,7 +254,7 @@ __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR,
         }
         __syncthreads();
         for (uint32_t j = tid; j < n; j += blockDim.x) {
-          if (j == p || !(XR[(size_t)j * s2 + cw] & cm)) continue;
+          if (j == p || !(XR[(size_t)cw * n + j] & cm)) continue;
           const uint32_t i = atomicAdd(&s_cnt, 1u);
           if (i < kRefList) list[i] = j;
           else s_more = 1;
@@ -260,45 +265,77 @@ __global__ void __launch_bounds__(kRefThreads) k_ref_collapse_rows(uint64_t *XR,
       const uint32_t cnt = s_cnt < kRefList ? s_cnt : kRefList;
       const bool more = s_more != 0;           // read before the next reset
       for (uint32_t w = tid; w < words; w += blockDim.x) {
-        const uint64_t xp = xp_row[w];
-        uint64_t zp = zp_row[w], sb = SB[w];
+        const uint64_t xp = xp_row[(size_t)w * n];
+        uint64_t zp = zp_row[(size_t)w * n], sb = SB[w];
         for (uint32_t i = 0; i < cnt; i++) {
           const uint32_t r = list[i];
           if (r == p) continue;
-          uint64_t *xt_p = XR + (size_t)r * s2 + w;
-          const uint64_t xt = *xt_p, zt = ZR[(size_t)r * s2 + w];
+          uint64_t *xt_p = XR + (size_t)w * n + r;
+          const uint64_t xt = *xt_p, zt = ZR[(size_t)w * n + r];
           sb ^= xp & zt & ~(xt ^ zp);
           *xt_p = xt ^ xp;
           zp ^= zt;
         }
-        zp_row[w] = zp;
+        zp_row[(size_t)w * n] = zp;
         SB[w] = sb;
       }
       __syncthreads();
       if (!more) break;
     }
     // H (X term at the pivot) or H_YZ (Y term) turns the column into +-Z_p.
-    if (tid == 0) s_bit = (zp_row[cw] & cm) ? 1u : 0u;
+    if (tid == 0) s_bit = (zp_row[(size_t)cw * n] & cm) ? 1u : 0u;
     __syncthreads();
     const bool yz = s_bit != 0;
     for (uint32_t w = tid; w < words; w += blockDim.x) {
-      const uint64_t x = xp_row[w], z = zp_row[w];
+      const uint64_t x = xp_row[(size_t)w * n], z = zp_row[(size_t)w * n];
       if (yz) {                                // X -> -X, Y -> Z, Z -> Y
         SB[w] ^= x & ~z;
-        xp_row[w] = x ^ z;
+        xp_row[(size_t)w * n] = x ^ z;
       } else {                                 // X <-> Z, Y -> -Y
         SB[w] ^= x & z;
-        xp_row[w] = z;
-        zp_row[w] = x;
+        xp_row[(size_t)w * n] = z;
+        zp_row[(size_t)w * n] = x;
       }
     }
     __syncthreads();
     if (tid == 0) s_bit = (SB[cw] & cm) ? 1u : 0u;
     __syncthreads();
     if (s_bit)                                 // X on the pivot: the result becomes 0
-      for (uint32_t w = tid; w < words; w += blockDim.x) SB[w] ^= zp_row[w];
+      for (uint32_t w = tid; w < words; w += blockDim.x) SB[w] ^= zp_row[(size_t)w * n];
     __syncthreads();
   }
+}
+
+// The tableau by columns (c[col][w]: bits of qubits 64 w .. 64 w + 63 of
+// column col, column stride nwp words) <-> by column groups (r[cw * n + j]:
+// bits of columns 64 cw .. 64 cw + 63 for qubit j): one wave per 64 x 64 bit
+// block, transposed in registers.
+__global__ void __launch_bounds__(256) k_ref_to_rows(const uint64_t *__restrict__ c, uint64_t *__restrict__ r,
+                                                     uint32_t n, uint32_t nwp, uint32_t groups) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;     // block (cw, w)
+  const uint32_t nw = (n + 63) / 64;
+  if (b >= (uint64_t)groups * nw) return;                                        // whole waves leave
+  const uint32_t cw = (uint32_t)(b / nw), w = (uint32_t)(b % nw);
+  const uint32_t col = cw * 64 + lane;
+  const uint64_t v = col < 2 * n ? c[(size_t)col * nwp + w] : 0;
+  const uint64_t y = bit_transpose64(v, lane);
+  const uint32_t j = w * 64 + lane;
+  if (j < n) r[(size_t)cw * n + j] = y;
+}
+
+__global__ void __launch_bounds__(256) k_ref_from_rows(const uint64_t *__restrict__ r, uint64_t *__restrict__ c,
+                                                       uint32_t n, uint32_t nwp, uint32_t groups) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nw = (n + 63) / 64;
+  if (b >= (uint64_t)groups * nw) return;
+  const uint32_t cw = (uint32_t)(b / nw), w = (uint32_t)(b % nw);
+  const uint32_t j = w * 64 + lane;
+  const uint64_t v = j < n ? r[(size_t)cw * n + j] : 0;
+  const uint64_t y = bit_transpose64(v, lane);
+  const uint32_t col = cw * 64 + lane;
+  if (col < 2 * n) c[(size_t)col * nwp + w] = y;
 }
 
 // Classically controlled Paulis: pairs (qubit, lookback); the Pauli is
@@ -500,18 +537,14 @@ int gpu_reference_sample(const std::vector<Node> &tree, uint64_t num_qubits, uin
         }
         if (h_rnd == 0) continue;
         // Random results: transpose, collapse them in order, transpose back.
-        if ((e = launch_transpose(t.xb, 2 * n, nwp, n, XR, s)) != hipSuccess ||
-            (e = launch_transpose(t.zb, 2 * n, nwp, n, ZR, s)) != hipSuccess) {
-          rc = fail(e, "tableau transpose");
-          break;
-        }
+        const uint32_t groups = (uint32_t)((2 * n + 63) / 64);
+        const dim3 tgrid((uint32_t)(((uint64_t)groups * nw * 64 + 255) / 256));
+        hipLaunchKernelGGL(k_ref_to_rows, tgrid, dim3(256), 0, s, t.xb, XR, (uint32_t)n, (uint32_t)nwp, groups);
+        hipLaunchKernelGGL(k_ref_to_rows, tgrid, dim3(256), 0, s, t.zb, ZR, (uint32_t)n, (uint32_t)nwp, groups);
         hipLaunchKernelGGL(k_ref_collapse_rows, dim3(1), dim3(kRefThreads), 0, s, XR, ZR, (uint64_t *)t.sb,
-                           (uint32_t)n, (uint32_t)s2, st.gate, tg, st.count, st.meas0, ref, (const uint32_t *)flag);
-        if ((e = launch_transpose(XR, n, s2, 2 * n, t.xb, s)) != hipSuccess ||
-            (e = launch_transpose(ZR, n, s2, 2 * n, t.zb, s)) != hipSuccess) {
-          rc = fail(e, "tableau transpose");
-          break;
-        }
+                           (uint32_t)n, st.gate, tg, st.count, st.meas0, ref, (const uint32_t *)flag);
+        hipLaunchKernelGGL(k_ref_from_rows, tgrid, dim3(256), 0, s, XR, t.xb, (uint32_t)n, (uint32_t)nwp, groups);
+        hipLaunchKernelGGL(k_ref_from_rows, tgrid, dim3(256), 0, s, ZR, t.zb, (uint32_t)n, (uint32_t)nwp, groups);
       }
     }
     if (rc) break;
