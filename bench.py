@@ -3,15 +3,16 @@ experiment (49 rounds, p = 1e-3, 65,536 shots) on one MI355X.
 
 One step = one pass of the whole sampling path over one batch of shots:
 frame initialisation, Clifford propagation, Pauli noise, resets, measurements
-(flip record written to HBM) and detection events + observable flips
-(stim_detector_sample).  Inputs (the compiled program and reference sample)
+and detection events + observable flips (stim_detector_sample: the frame
+kernel forms the events from a ring of its recent flips).  Inputs (the compiled program and reference sample)
 are resident on the GPU before the timed region; compile and reference
 ("analysis") time is reported separately.
 
 Prints one JSON line.  Fields beyond the driver's contract:
-  roofline      -- for the frame kernel (k_frame, HIP events on its stream):
-                   compulsory bytes (the record it writes) against HBM peak,
-                   measured HBM traffic when the counters match the sources
+  roofline      -- for the step's frame kernel (k_frame, HIP events on its
+                   stream): compulsory bytes (the event tables it writes)
+                   against HBM peak, measured HBM traffic when the counters
+                   match the sources
   cpu_baseline  -- the oracle (-O3 -march=native) timed on this host on a
                    bounded shot sample, at all usable CPUs and at one
   configs       -- d=3 x 1,024, d=15 x 2^20 and d=49 x 262,144 shots:
@@ -440,7 +441,7 @@ def main():
                     help="only compute the GPU reference sample of the distance-D surface code twice "
                          "(for profiling)")
     ap.add_argument("--frame-probe", action="store_true",
-                    help="only sample the d=49 measurement record 3 times (for profiling k_noise_gen and "
+                    help="only run the d=49 step (detection events) 3 times (for profiling k_noise_gen and "
                          "k_frame)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 2 GiB device-to-device three times (HBM counter calibration)")
@@ -465,9 +466,11 @@ def main():
 
     if args.frame_probe:
         circ = stim_gpu.Circuit(workloads.surface_code(D, ROUNDS, P))
-        meas = torch.empty((circ.num_measurements, (SHOTS + 63) // 64), dtype=torch.int64, device="cuda")
+        W = (SHOTS + 63) // 64
+        det = torch.empty((circ.num_detectors, W), dtype=torch.int64, device="cuda")
+        obs = torch.empty((max(circ.num_observables, 1), W), dtype=torch.int64, device="cuda")
         for _ in range(3):
-            stim_gpu.stim_frame_sample(circ.handle, SEED, 0, SHOTS, meas)
+            stim_gpu.stim_detector_sample(circ.handle, SEED, 0, SHOTS, det, obs)
         torch.cuda.synchronize()
         print(json.dumps({"frame_probe": f"d={D}", "calls": 3}), flush=True)
         return
@@ -521,12 +524,23 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = G * SHOTS / (dt / args.steps)
 
+    # The step's kernels: the noise pre-pass and the frame kernel, which forms
+    # the detection events itself (HIP events recorded by the library on the
+    # stream the kernels run on).
+    reps = max(5, args.steps)
+    stim_gpu.stim_kernel_timing(True)
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    det_gen_ms, det_frame_ms, det_passes = stim_gpu.stim_kernel_times()
+    stim_gpu.stim_kernel_timing(False)
+    det_gen_ms, det_frame_ms = det_gen_ms / det_passes, det_frame_ms / det_passes
+
     # One sampling pass in measurement mode = the noise pre-pass kernel plus
     # the frame kernel.  The pass is timed with HIP events on the stream it
     # runs on; the library's own events split it per kernel.
     for _ in range(2):
         stim_gpu.stim_frame_sample(circ.handle, SEED, 0, SHOTS, meas, stream)
-    reps = max(5, args.steps)
     torch.cuda.synchronize()
     stim_gpu.stim_kernel_timing(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -539,12 +553,14 @@ def main():
     stim_gpu.stim_kernel_timing(False)
     pass_ms = ev0.elapsed_time(ev1) / reps
     gen_ms, kframe_ms = gen_ms / passes, kframe_ms / passes
-    # Dominant kernel: k_frame.  Its algorithmic bytes are the compulsory
-    # ones, the measurement record it writes (M S / 8 bytes: one bit per
-    # measurement and shot; the frame stays on chip).
+    # Dominant kernel: k_frame of the step (detector mode).  Its algorithmic
+    # bytes are the compulsory ones, the event and observable tables it writes
+    # ((D + L) S / 8 bytes: one bit per detector and shot; the frame stays on
+    # chip, the flip ring in the caches).
+    event_bytes = (Dn + L) * SHOTS / 8
     record_bytes = M * SHOTS / 8
     per_op_bytes = streaming_bytes(D, ROUNDS, P, SHOTS)
-    achieved = record_bytes / (kframe_ms * 1e-3) / 1e9
+    achieved = event_bytes / (det_frame_ms * 1e-3) / 1e9
     digest = sources_digest()
     fresh = PMC_KIB is not None and PMC_SOURCES == digest
     traffic = None
@@ -552,14 +568,16 @@ def main():
         f, w = PMC_KIB["k_frame"]
         traffic = 1024 * (f * FETCH_SCALE + w * WRITE_SCALE)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_frame (measurement mode)",
-                "launch_ms": kframe_ms, "algorithmic_bytes": record_bytes,
-                "algorithmic_bytes_basis": "compulsory: the measurement record, M*S/8 bytes (frame kept in LDS)",
-                "measured_hbm_frac": (traffic / (kframe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                "traffic_over_algorithmic": (traffic / record_bytes) if traffic else None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_frame (detector mode: events formed in the walk)",
+                "launch_ms": det_frame_ms, "algorithmic_bytes": event_bytes,
+                "algorithmic_bytes_basis": "compulsory: the event and observable tables, (D+L)*S/8 bytes "
+                                           "(frame kept in LDS)",
+                "measured_hbm_frac": (traffic / (det_frame_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                "traffic_over_algorithmic": (traffic / event_bytes) if traffic else None,
                 "per_op_streaming_bytes": per_op_bytes,
                 "traffic_over_per_op_streaming": (traffic / per_op_bytes) if traffic else None,
-                "pass_ms": pass_ms, "k_noise_gen_ms": gen_ms,
+                "k_noise_gen_ms": det_gen_ms,
                 "counters": PMC_PROFILE if fresh else f"none for library sources {digest}"}
 
     out = {
@@ -580,7 +598,9 @@ def main():
                    "shots": SHOTS, "seed": SEED, "num_qubits": circ.num_qubits, "gate_targets": G,
                    "measurements": M, "detectors": Dn},
         "roofline": roofline,
-        "meas_mode": {"ms": pass_ms, "shot_gates_per_s": G * SHOTS / (pass_ms * 1e-3)},
+        "meas_mode": {"ms": pass_ms, "shot_gates_per_s": G * SHOTS / (pass_ms * 1e-3),
+                      "k_noise_gen_ms": gen_ms, "k_frame_ms": kframe_ms, "record_bytes": record_bytes,
+                      "k_frame_record_GBs": record_bytes / (kframe_ms * 1e-3) / 1e9},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
     out["host_copy"] = bench_host_copy(det, obs, stream, ms_per_step, G)

@@ -112,7 +112,13 @@ int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint
 /* Samples detection events (Sec. 5.6) and observable flips of the same shots.
  * out_det: device [num_detectors][W]; out_obs: device [num_observables][W] or
  * NULL.  Event = XOR of the detector's measurement flips (the reference bits
- * cancel because detectors are deterministic in the noiseless circuit). */
+ * cancel because detectors are deterministic in the noiseless circuit).
+ * The frame walk forms the events itself from a per-workgroup ring of its
+ * recent flips (longest detector, observable or feedback lookback plus the
+ * largest measurement instruction, at most the whole record, in rows of the
+ * tile's words) when those
+ * rings fit in 512 MiB; otherwise (or with STIM_WALK_EVENTS=0) it writes the
+ * flip record and a second kernel forms the events.  Same bits either way. */
 int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
                          uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
 
@@ -163,7 +169,8 @@ int stim_error_sets(stim_circuit *c, uint64_t *num_sets, uint64_t *num_entries, 
  * outputs, for admission control.  mode 0: stim_frame_sample (noise records
  * of the pre-pass and their tables; the per-workgroup frame slots of circuits
  * too large for LDS); mode 1: stim_detector_sample (the same plus the flip
- * table, one ceil(num_shots / 64)-word row per measurement); mode 2:
+ * rings when the walk forms the events, else the flip table, one
+ * ceil(num_shots / 64)-word row per measurement); mode 2:
  * stim_sparse_detector_sample (0: it allocates nothing per call).  Host only;
  * *bytes (host) receives the size.  STIM_E_INVALID_ARG for a null argument or
  * another mode. */

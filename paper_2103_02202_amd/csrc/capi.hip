@@ -47,6 +47,7 @@ int hip_error(hipError_t e, const char *what) {
 // Device-resident copy of a compiled circuit.
 struct DeviceCopy {
   DevOp *ops = nullptr;
+  DevOp *event_ops = nullptr;       // the program with event ops
   uint32_t *targets = nullptr;
   uint64_t *thresholds = nullptr;
   uint64_t *ref = nullptr;
@@ -161,7 +162,8 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
   }
   DeviceCopy d;
   const Program &P = c->prog;
-  if ((e = upload(P.ops, &d.ops, s)) != hipSuccess || (e = upload(P.targets, &d.targets, s)) != hipSuccess ||
+  if ((e = upload(P.ops, &d.ops, s)) != hipSuccess || (e = upload(P.event_ops, &d.event_ops, s)) != hipSuccess ||
+      (e = upload(P.targets, &d.targets, s)) != hipSuccess ||
       (e = upload(P.thresholds, &d.thresholds, s)) != hipSuccess || (e = upload(c->ref, &d.ref, s)) != hipSuccess ||
       (e = upload(P.det_offsets, &d.det_off, s)) != hipSuccess ||
       (e = upload(P.det_indices, &d.det_idx, s)) != hipSuccess ||
@@ -524,9 +526,61 @@ uint64_t pass_scratch_bytes(const Program &P, uint64_t num_shots, int dev) {
   return bytes;
 }
 
-// Runs the frame kernel; ref == nullptr writes raw flips.
+// Detection events formed in the walk (Sec. 5.6): each workgroup keeps its
+// recent flips in a ring of max_lookback + max_measure_op rows (at most the
+// record's length) of T words, and
+// detector and observable ops write the event tables directly, so the flip
+// record is never written out and read back.  Rings are per workgroup slot:
+// one workgroup per tile for an LDS-resident frame (capped by a memory
+// budget, beyond which workgroups take several tiles in turn), the global
+// frame's slots otherwise.  Off (flip record + event kernel) when
+// STIM_WALK_EVENTS=0, or when the rings would exceed the budget;
+// STIM_WALK_EVENT_SLOTS caps the slots (workgroups then take tiles in turn).
+constexpr uint64_t kRingBudget = 512ull << 20;
+
+struct WalkEvents {
+  uint64_t *det_out = nullptr, *obs_out = nullptr;
+  uint32_t num_obs = 0;
+};
+
+// A ring as long as the whole record never wraps: no longer is needed.
+uint32_t ring_rows(const Program &P) {
+  const uint64_t r = std::min<uint64_t>((uint64_t)P.max_lookback + P.max_measure_op, P.num_measurements);
+  return (uint32_t)std::max<uint64_t>(1, r);
+}
+
+// Ring slots of a walk with events for num_shots shots (0: not possible).
+uint64_t walk_event_slots(const Program &P, uint64_t num_shots, int dev) {
+  const char *env = std::getenv("STIM_WALK_EVENTS");
+  if (env && std::strcmp(env, "0") == 0) return 0;
+  if (P.num_detectors + P.num_observables == 0) return 0;
+  if ((uint64_t)P.max_lookback + P.max_measure_op >= (1ull << 31)) return 0;
+  const uint64_t W = (num_shots + 63) / 64;
+  const FrameConfig cfg = choose_config(P.num_qubits, W);
+  const uint64_t ntiles = (W + cfg.tile_words - 1) / cfg.tile_words;
+  const uint64_t slot_bytes = (uint64_t)ring_rows(P) * cfg.tile_words * sizeof(uint64_t);
+  uint64_t slots;
+  if (cfg.in_lds) {
+    const uint64_t fit = kRingBudget / slot_bytes;
+    slots = std::min<uint64_t>(ntiles, std::max<uint64_t>(fit, (uint64_t)cu_count(dev)));
+  } else {
+    slots = global_frame_slots(dev, ntiles);
+  }
+  if (const char *v = std::getenv("STIM_WALK_EVENT_SLOTS")) slots = std::min<uint64_t>(slots, std::max(1L, atol(v)));
+  if (slots == 0 || slots > 0xFFFFFFFFull || slots * slot_bytes > kRingBudget) return 0;
+  return slots;
+}
+
+uint64_t walk_event_bytes(const Program &P, uint64_t num_shots, int dev) {
+  const uint64_t slots = walk_event_slots(P, num_shots, dev);
+  const FrameConfig cfg = choose_config(P.num_qubits, (num_shots + 63) / 64);
+  return slots * ring_rows(P) * cfg.tile_words * sizeof(uint64_t);
+}
+
+// Runs the frame kernel; ref == nullptr writes raw flips.  With `ev`, the walk
+// forms detection events and observables instead of writing `out`.
 int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
-              const uint64_t *ref, uint64_t *out, hipStream_t s) {
+              const uint64_t *ref, uint64_t *out, hipStream_t s, const WalkEvents *ev = nullptr) {
   const uint64_t W = (num_shots + 63) / 64;
   FrameConfig cfg = choose_config(c->prog.num_qubits, W);
   FrameParams p{};
@@ -645,11 +699,11 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     p.noise_tiles = (uint32_t)ntiles;
     p.noise_instances = (uint32_t)ninst;
   }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   if (!cfg.in_lds) {
     // One scratch slot per workgroup in flight: about one workgroup per CU, so
     // that the frames in flight stay within the last-level cache.
-    int dev = 0;
-    (void)hipGetDevice(&dev);
     cfg.slots = (uint32_t)global_frame_slots(dev, ntiles);
     const uint64_t tiles = cfg.slots;
     size_t bytes = (size_t)tiles * cfg.tile_words * 16 * (c->prog.num_qubits + 1);     // + the dummy row
@@ -659,6 +713,30 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
       return set_error(STIM_E_OOM, "frame scratch allocation failed");
     }
   }
+  if (ev) {
+    const uint64_t slots = walk_event_slots(P, num_shots, dev);
+    if (slots == 0) {
+      if (p.scratch) (void)hipFreeAsync(p.scratch, s);
+      free_prepass();
+      drop_events();
+      return set_error(STIM_E_UNSUPPORTED, "detection events cannot be formed in the walk");
+    }
+    cfg.slots = (uint32_t)slots;
+    p.ops = d->event_ops;
+    p.num_ops = (uint32_t)P.event_ops.size();
+    p.ring_rows = ring_rows(P);
+    p.det_out = ev->det_out;
+    p.obs_out = ev->obs_out;
+    p.num_obs = ev->obs_out ? ev->num_obs : 0;
+    p.out = nullptr;
+    if ((e = hipMallocAsync((void **)&p.ring, slots * p.ring_rows * cfg.tile_words * sizeof(uint64_t), s)) !=
+        hipSuccess) {
+      if (p.scratch) (void)hipFreeAsync(p.scratch, s);
+      free_prepass();
+      drop_events();
+      return set_error(STIM_E_OOM, "flip ring allocation failed");
+    }
+  }
   if (c->prog.num_measurements > 0 || c->prog.num_qubits > 0) {
     if (timed) {
       if (!prepass) (void)hipEventRecord(tev.start, s);
@@ -666,6 +744,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     }
     if ((e = launch_frame(p, cfg, s)) != hipSuccess) {
       if (p.scratch) (void)hipFreeAsync(p.scratch, s);
+      if (p.ring) (void)hipFreeAsync(p.ring, s);
       free_prepass();
       drop_events();
       return hip_error(e, "frame kernel launch");
@@ -681,6 +760,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   drop_events();
   free_prepass();
   if (p.scratch && (e = hipFreeAsync(p.scratch, s)) != hipSuccess) return hip_error(e, "hipFreeAsync");
+  if (p.ring && (e = hipFreeAsync(p.ring, s)) != hipSuccess) return hip_error(e, "hipFreeAsync");
   return STIM_OK;
 }
 
@@ -1240,7 +1320,7 @@ void stim_circuit_free(stim_circuit *c) {
   for (auto &kv : c->dev) {
     (void)hipSetDevice(kv.first);
     DeviceCopy &d = kv.second;
-    void *ptrs[] = {d.ops,       d.targets,     d.thresholds, d.ref,     d.det_off,
+    void *ptrs[] = {d.ops,       d.event_ops,   d.targets,     d.thresholds, d.ref,     d.det_off,
                     d.det_idx,   d.obs_off,     d.obs_idx,    d.det_order, d.noise_pc,
                     d.noise_instr, d.gen_base, d.set_off,    d.set_lanes, d.wb_e0,
                     d.wb_e1,       d.wb_base};
@@ -1300,6 +1380,15 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
     std::lock_guard<std::mutex> lock(c->mu);
     if ((rc = ensure_reference(c, s, true))) return rc;
     if ((rc = ensure_device(c, s, &d))) return rc;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (walk_event_slots(c->prog, num_shots, dev) > 0) {
+    WalkEvents ev;
+    ev.det_out = out_det;
+    ev.obs_out = c->prog.num_observables > 0 ? out_obs : nullptr;
+    ev.num_obs = (uint32_t)c->prog.num_observables;
+    return run_frame(c, d, seed, shot_offset, num_shots, nullptr, nullptr, s, &ev);
   }
   const uint64_t W = (num_shots + 63) / 64;
   uint64_t *flips = nullptr;
@@ -1492,7 +1581,11 @@ int stim_sample_scratch_bytes(stim_circuit *c, uint64_t num_shots, int mode, uin
   (void)hipGetDevice(&dev);
   const Program &P = c->prog;
   uint64_t b = pass_scratch_bytes(P, num_shots, dev);
-  if (mode == 1) b += std::max<uint64_t>(P.num_measurements, 1) * ((num_shots + 63) / 64) * sizeof(uint64_t);
+  if (mode == 1) {
+    // The flip rings when the walk forms the events, else the flip record.
+    const uint64_t ring = walk_event_bytes(P, num_shots, dev);
+    b += ring ? ring : std::max<uint64_t>(P.num_measurements, 1) * ((num_shots + 63) / 64) * sizeof(uint64_t);
+  }
   *bytes = b;
   return STIM_OK;
 }

@@ -194,6 +194,27 @@ struct Lowering {
   std::unordered_map<const Node *, std::vector<uint32_t>> slot_targets;  // collapse slots -> target index
   std::unordered_map<const Node *, std::vector<uint32_t>> fb_targets;    // controlled pairs -> qubit word index
   uint32_t depth = 0;
+  // Consecutive DETECTOR lines not yet emitted (no op between them).
+  std::vector<const Node *> dets;
+
+  // Emits the pending detectors as one DET op: lookback lists padded with
+  // zeros to a common even length, starting on an even target index (pairs
+  // are read as one 8-byte word).
+  void flush_detectors() {
+    if (dets.empty()) return;
+    size_t c = 2;
+    for (const Node *d : dets) c = std::max(c, (d->targets.size() + 1) & ~(size_t)1);
+    if (prog.targets.size() % 2) prog.targets.push_back(0);
+    DevOp op{};
+    op.code = OP_DET;
+    op.n = (uint32_t)dets.size();
+    op.toff = (uint32_t)prog.targets.size();
+    op.aux = (uint32_t)c;
+    for (const Node *d : dets)
+      for (size_t i = 0; i < c; i++) prog.targets.push_back(i < d->targets.size() ? d->targets[i] : 0u);
+    prog.ops.push_back(op);
+    dets.clear();
+  }
 
   uint32_t threshold_row(double p) {
     uint64_t bits;
@@ -254,6 +275,7 @@ struct Lowering {
       while (s < pairs && is_fb(s) == kind) {
         uint32_t a = n.targets[2 * s], b = n.targets[2 * s + 1];
         if (kind && (a & TGT_REC)) std::swap(a, b);          // (qubit, record)
+        if (kind) prog.max_lookback = std::max(prog.max_lookback, b & ~TGT_REC);
         if (used.count(a) || (!kind && used.count(b))) break;
         used[a] = 1;
         if (!kind) used[b] = 1;
@@ -270,6 +292,31 @@ struct Lowering {
   }
 
   void emit_line(const Node &n) {
+    // Event ops take no flat index of their own: the DETECTOR and
+    // OBSERVABLE_INCLUDE lines stay counted in the lead of the next op.
+    if (n.gate == G_DETECTOR || n.gate == G_OBSERVABLE_INCLUDE) {
+      pending_lead++;
+      for (uint32_t k : n.targets) prog.max_lookback = std::max(prog.max_lookback, k);
+      if (n.gate == G_DETECTOR) {       // an empty one is an event row of zeros
+        dets.push_back(&n);
+        return;
+      }
+      if (n.targets.empty()) return;
+      flush_detectors();
+      DevOp op{};
+      op.code = OP_OBS;
+      op.n = (uint32_t)n.targets.size();
+      op.toff = (uint32_t)prog.targets.size();
+      op.aux = (uint32_t)n.p;
+      prog.targets.insert(prog.targets.end(), n.targets.begin(), n.targets.end());
+      prog.ops.push_back(op);
+      return;
+    }
+    if (n.gate == G_QUBIT_COORDS || n.gate == G_SHIFT_COORDS || n.gate == G_TICK) {
+      pending_lead++;
+      return;
+    }
+    flush_detectors();
     if (n.gate == G_CX || n.gate == G_CY || n.gate == G_CZ) {
       bool controlled = false;
       for (uint32_t t : n.targets) controlled |= (t & TGT_REC) != 0;
@@ -317,6 +364,7 @@ struct Lowering {
         s++;
         op.n++;
       }
+      if (code == OP_M || code == OP_MR) prog.max_measure_op = std::max(prog.max_measure_op, op.n);
       prog.ops.push_back(op);
       first = false;
     }
@@ -329,6 +377,7 @@ struct Lowering {
         emit_line(n);
         continue;
       }
+      flush_detectors();
       depth++;
       if (depth > prog.max_loop_depth) prog.max_loop_depth = depth;
       uint32_t begin = (uint32_t)prog.ops.size();
@@ -339,6 +388,7 @@ struct Lowering {
       pending_lead = 0;
       prog.ops.push_back(b);
       emit_block(n.body);
+      flush_detectors();
       DevOp e{};
       e.code = OP_LOOP_END;
       e.lead = pending_lead;
@@ -545,6 +595,7 @@ Program compile_program(const std::vector<Node> &tree) {
   for (uint64_t q = 0; q < n; q++) L.prog.targets.push_back((uint32_t)q);
   L.prog.ops.push_back(init);
   L.emit_block(tree);   // trailing annotations need no op: nothing after them draws bits
+  L.flush_detectors();
   // Unrolled walk.
   Walker w{L};
   w.pending.assign(n, Walker::NONE);
@@ -601,6 +652,50 @@ Program compile_program(const std::vector<Node> &tree) {
       }
     }
   }
+  // Mark dead Z randomisations on init and collapse targets, and flag the
+  // collapse ops whose every randomisation is live.
+  for (DevOp &op : L.prog.ops) {
+    uint32_t code = op.code & 0xFFFF;
+    if (code != OP_INIT && code != OP_R && code != OP_M && code != OP_MR) continue;
+    bool all_live = true;
+    for (uint32_t k = 0; k < op.n; k++)
+      if (!w.site_live[op.toff + k]) {
+        L.prog.targets[op.toff + k] |= TGT_DEAD_ZRAND;
+        all_live = false;
+      }
+    if (all_live) op.code |= OPF_ZRAND_LIVE;
+  }
+  // Mark local feedback pairs, and the feedback ops whose pairs all are.
+  for (DevOp &op : L.prog.ops) {
+    const uint32_t code = op.code & 0xFFFF;
+    if (code < OP_FB_X || code > OP_FB_Z) continue;
+    bool all_local = true;
+    for (uint32_t k = 0; k < op.n; k++) {
+      const size_t t = op.toff + 2 * (size_t)k;
+      if (w.fb_local[t]) L.prog.targets[t] |= TGT_FB_LOCAL;
+      else all_local = false;
+    }
+    if (all_local && op.n > 0) op.code |= OPF_FB_LOCAL;
+  }
+  // Split off the event ops: `ops` keeps everything else, with loop targets
+  // renumbered.
+  {
+    Program &P = L.prog;
+    P.event_ops = P.ops;
+    std::vector<uint32_t> newpc(P.event_ops.size() + 1, 0);
+    P.ops.clear();
+    for (size_t pc = 0; pc < P.event_ops.size(); pc++) {
+      newpc[pc] = (uint32_t)P.ops.size();
+      const uint32_t code = P.event_ops[pc].code & 0xFFFF;
+      if (code != OP_DET && code != OP_OBS) P.ops.push_back(P.event_ops[pc]);
+    }
+    newpc[P.event_ops.size()] = (uint32_t)P.ops.size();
+    for (DevOp &op : P.ops) {
+      const uint32_t code = op.code & 0xFFFF;
+      if (code == OP_LOOP_BEGIN) op.aux2 = newpc[op.aux2];
+      if (code == OP_LOOP_END) op.aux = newpc[op.aux];
+    }
+  }
   // Noise-op executions in walk order (same control flow as the kernels).
   {
     const size_t kMaxInstances = 65535;
@@ -630,31 +725,6 @@ Program compile_program(const std::vector<Node> &tree) {
       }
     }
     if (!ok) { P.noise_pc.clear(); P.noise_instr.clear(); }
-  }
-  // Mark dead Z randomisations on init and collapse targets, and flag the
-  // collapse ops whose every randomisation is live.
-  for (DevOp &op : L.prog.ops) {
-    uint32_t code = op.code & 0xFFFF;
-    if (code != OP_INIT && code != OP_R && code != OP_M && code != OP_MR) continue;
-    bool all_live = true;
-    for (uint32_t k = 0; k < op.n; k++)
-      if (!w.site_live[op.toff + k]) {
-        L.prog.targets[op.toff + k] |= TGT_DEAD_ZRAND;
-        all_live = false;
-      }
-    if (all_live) op.code |= OPF_ZRAND_LIVE;
-  }
-  // Mark local feedback pairs, and the feedback ops whose pairs all are.
-  for (DevOp &op : L.prog.ops) {
-    const uint32_t code = op.code & 0xFFFF;
-    if (code < OP_FB_X || code > OP_FB_Z) continue;
-    bool all_local = true;
-    for (uint32_t k = 0; k < op.n; k++) {
-      const size_t t = op.toff + 2 * (size_t)k;
-      if (w.fb_local[t]) L.prog.targets[t] |= TGT_FB_LOCAL;
-      else all_local = false;
-    }
-    if (all_local && op.n > 0) op.code |= OPF_FB_LOCAL;
   }
   return L.prog;
 }

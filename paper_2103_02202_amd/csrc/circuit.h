@@ -55,6 +55,12 @@ enum OpCode : uint32_t {
   // frame of shots whose result k measurements back differs from the
   // reference's takes the Pauli.
   OP_FB_X, OP_FB_Y, OP_FB_Z,
+  // Detection events formed during the walk (Sec. 5.6; used only when the
+  // walk keeps recent measurement flips in a ring): DET = op.n consecutive
+  // detectors, each the XOR of op.aux lookbacks k (flip of the measurement k
+  // back; zero entries pad a detector's list); OBS = observable op.aux takes
+  // the XOR of op.n lookbacks.  Neither changes the frame.
+  OP_DET, OP_OBS,
   OP_COUNT
 };
 
@@ -89,7 +95,11 @@ struct DevOp {
 };
 
 struct Program {
+  // The device program without event ops (DET / OBS), and the same program
+  // with them (for walks that form detection events; loop targets renumbered,
+  // every other entry equal to its counterpart in `ops`).
   std::vector<DevOp> ops;
+  std::vector<DevOp> event_ops;
   std::vector<uint32_t> targets;
   std::vector<uint64_t> thresholds;        // [rows][64]
   std::vector<uint32_t> det_offsets;       // CSR over detectors, size D + 1
@@ -103,6 +113,10 @@ struct Program {
   uint64_t num_qubits = 0, num_measurements = 0, num_detectors = 0, num_observables = 0;
   uint64_t num_gate_targets = 0, num_noise_targets = 0, num_instructions = 0;
   uint32_t max_loop_depth = 0;
+  // Largest lookback k of a detector, observable or classically controlled
+  // pair, and most measurements of one op: a ring of max_lookback +
+  // max_measure_op rows holds every flip an event op or feedback reads.
+  uint32_t max_lookback = 0, max_measure_op = 0;
   // Every execution of a noise op in walk order: its pc and flat instruction
   // index (empty when there are too many to tabulate).
   std::vector<uint32_t> noise_pc;

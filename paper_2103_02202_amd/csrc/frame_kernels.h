@@ -10,7 +10,7 @@
 namespace stimgpu {
 
 struct FrameParams {
-  const DevOp *ops;
+  const DevOp *ops;             // the program; with event ops when ring != NULL
   uint32_t num_ops;
   uint32_t num_qubits;
   const uint32_t *targets;
@@ -30,6 +30,16 @@ struct FrameParams {
   const uint4 *noise_rec;       // 16-byte records
   uint32_t noise_tiles;
   uint32_t noise_instances;
+  // Detection events formed in the walk (ring != NULL): measurements write
+  // their flips into the workgroup's ring of ring_rows rows of T words (slot
+  // s at ring + s ring_rows T) instead of `out`; detector ops write rows of
+  // det_out, observable ops XOR into rows of obs_out (NULL: skipped; its
+  // num_obs rows are cleared first), both with row stride out_stride.
+  uint64_t *ring;
+  uint64_t *det_out;
+  uint64_t *obs_out;
+  uint32_t ring_rows;
+  uint32_t num_obs;
 };
 
 // Record count meaning "draw this noise op inline".
@@ -65,7 +75,7 @@ struct FrameConfig {
   int tile_words;               // T: 1, 2, 4, 8, 16 or 32
   bool in_lds;
   uint32_t threads;
-  uint32_t slots = 0;           // global frame: workgroups (and scratch slots); 0 = one per tile
+  uint32_t slots = 0;           // workgroups (global frame or ring slots); 0 = one per tile
   bool wave = false;            // batched launches: one wave per tile (k_batch_wave)
 };
 

@@ -22,6 +22,7 @@
 
 #include <type_traits>
 
+#include "bit_transpose.h"
 #include "circuit.h"
 #include "frame_kernels.h"
 #include "lds_attr.h"
@@ -209,16 +210,17 @@ __device__ __forceinline__ void noise_op(const FrameParams &p, const Tile<T, IN_
 // Every thread runs at least one pass, and every load of a pass is issued
 // unconditionally (clamped indices), then `after_loads` runs: loads complete in issue order, so the loads it
 // issues stay in flight while the pass waits only for its own.
-template <int T, bool IN_LDS, bool WAVE, typename AfterLoads>
+template <int T, bool IN_LDS, bool WAVE, bool EVENTS, typename AfterLoads>
 __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
-                                            uint32_t code, uint64_t instr, uint64_t meas, AfterLoads after_loads) {
+                                            uint32_t code, uint64_t instr, uint64_t meas, uint64_t *ring,
+                                            uint32_t ring_pos, AfterLoads after_loads) {
   constexpr int V = 2;
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
   const uint32_t g_lo = s_lo >> 2, ngroups = ((s_hi - 1) >> 2) - g_lo + 1;
   const uint32_t cand = ngroups * T;
   const uint32_t *tg = p.targets + op.toff;
   const bool measures = code == OP_M || code == OP_MR;
-  const bool use_ref = measures && p.ref != nullptr;
+  const bool use_ref = !EVENTS && measures && p.ref != nullptr;      // events: raw flips
   const bool all_live = (op.code & OPF_ZRAND_LIVE) != 0;       // uniform
   const uint32_t stride = team_size<WAVE>();
   uint32_t base = team_tid<WAVE>();
@@ -281,7 +283,12 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
           const uint64_t refw = (m >> 6) == (m0 >> 6) ? rw[v][0] : rw[v][1];
           if (use_ref && ((refw >> (m & 63)) & 1)) x = ~x;
           if (tl.tw0 + j == p.num_words - 1) x &= p.tail_mask;
-          p.out[m * p.out_stride + tl.tw0 + j] = x;
+          if constexpr (EVENTS) {
+            const uint32_t row = ring_pos + k < p.ring_rows ? ring_pos + k : ring_pos + k - p.ring_rows;
+            ring[(size_t)row * T + j] = x;
+          } else {
+            p.out[m * p.out_stride + tl.tw0 + j] = x;
+          }
         }
         if (code == OP_M) {
           if (!dead) tl.FZ[ix] ^= zr;
@@ -389,6 +396,108 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
   }
 }
 
+// Ring row of the measurement `back` measurements before the one at ring row
+// `pos` (1 <= back < rows).
+__device__ __forceinline__ uint32_t ring_back(uint32_t pos, uint32_t back, uint32_t rows) {
+  return pos >= back ? pos - back : pos + rows - back;
+}
+
+// Detection events formed in the walk (Sec. 5.6): detector i of the op is the
+// XOR of the flips its lookbacks name, read from the ring (written before the
+// last full barrier), and goes straight to its row of det_out.  An item is a
+// (detector, C words) pair; a thread takes up to U items at once and issues
+// their loads together.  The op ends with no barrier: it writes nothing the
+// team reads, and the ring rows it reads are not rewritten before the next
+// measurement op's own barrier (the ring holds the longest lookback plus the
+// largest measurement op).
+template <int T, bool IN_LDS, bool WAVE>
+__device__ __forceinline__ void detector_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
+                                            const uint64_t *ring, uint32_t ring_pos, uint32_t det) {
+  constexpr int U = 3;
+  constexpr uint32_t C = T >= 2 ? 2 : 1;
+  constexpr uint32_t CPT = T / C;
+  typedef uint64_t U64x2v __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<C == 2, U64x2v, uint64_t>::type Vec;
+  const uint32_t c = op.aux;                       // lookbacks per detector, even
+  const uint32_t items = op.n * CPT;
+  const uint32_t *tg = p.targets + op.toff;
+  const uint32_t R = p.ring_rows;
+  const uint32_t tsize = team_size<WAVE>();
+  for (uint32_t base = team_tid<WAVE>(); base < items; base += U * tsize) {
+    uint32_t k[U], j[U];
+    Vec acc[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t it = base + u * tsize;
+      k[u] = it < items ? it / CPT : 0u;
+      j[u] = (it % CPT) * C;
+      acc[u] = Vec(0);
+    }
+    for (uint32_t r = 0; r < c; r += 2) {
+      uint2 lb[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) lb[u] = *reinterpret_cast<const uint2 *>(tg + (size_t)k[u] * c + r);
+      // Every load is issued (a padding entry reads the row one back and its
+      // value is dropped), so that they are all in flight at once.
+      Vec va[U], vb[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const uint32_t ra = ring_back(ring_pos, lb[u].x ? lb[u].x : 1u, R);
+        const uint32_t rb = ring_back(ring_pos, lb[u].y ? lb[u].y : 1u, R);
+        va[u] = *reinterpret_cast<const Vec *>(ring + ra * T + j[u]);
+        vb[u] = *reinterpret_cast<const Vec *>(ring + rb * T + j[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        acc[u] ^= lb[u].x ? va[u] : Vec(0);
+        acc[u] ^= lb[u].y ? vb[u] : Vec(0);
+      }
+    }
+    // A whole pair goes out as one 16-byte store when rows start 16-byte
+    // aligned (even row stride) and both words are in range: one memory
+    // request per item.
+    const bool whole = (p.out_stride & 1) == 0 && ((uintptr_t)p.det_out & 15) == 0;       // uniform
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t it = base + u * tsize;
+      if (it >= items) continue;
+      uint64_t *dst = p.det_out + (uint64_t)(det + k[u]) * p.out_stride + tl.tw0 + j[u];
+      if constexpr (C == 2) {
+        if (whole && (int)j[u] + 1 < tl.valid) {
+          *reinterpret_cast<Vec *>(dst) = acc[u];
+        } else {
+          if ((int)j[u] < tl.valid) dst[0] = acc[u][0];
+          if ((int)j[u] + 1 < tl.valid) dst[1] = acc[u][1];
+        }
+      } else {
+        if ((int)j[u] < tl.valid) dst[0] = acc[u];
+      }
+    }
+  }
+}
+
+// Observable op: row op.aux of obs_out takes the XOR of the op's lookbacks.
+// Item = (lookback, word); each wave XORs its items per word across lanes
+// (lane l holds word l mod T, and T divides 64) and lanes 0 .. T-1 fold the
+// result into the row with one atomic XOR per word: several waves, and later
+// ops of the same observable, add to one word.
+template <int T, bool IN_LDS, bool WAVE>
+__device__ __forceinline__ void observable_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
+                                              const uint64_t *ring, uint32_t ring_pos) {
+  const uint32_t items = op.n * T;
+  const uint32_t *tg = p.targets + op.toff;
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t *dst = p.obs_out + (size_t)op.aux * p.out_stride + tl.tw0;
+  for (uint32_t base = team_tid<WAVE>() - lane; base < items; base += team_size<WAVE>()) {   // uniform per wave
+    const uint32_t it = base + lane;
+    uint64_t v = 0;
+    if (it < items) v = ring[(size_t)ring_back(ring_pos, tg[it / T], p.ring_rows) * T + it % T];
+#pragma unroll
+    for (uint32_t d = T; d < 64; d <<= 1) v ^= shfl_xor64(v, (int)d);
+    if (lane < (uint32_t)T && (int)lane < tl.valid) atomicXor((unsigned long long *)(dst + lane), (unsigned long long)v);
+  }
+}
+
 // Classically controlled Pauli (Sec. 3, tracking corrections): for each pair
 // (qubit, lookback k) and word of the tile, the shots whose result k
 // measurements back differs from the reference's take the Pauli into their
@@ -400,9 +509,9 @@ __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, 
 // acted on the qubit since) takes the difference from the qubit's own frame
 // x bit instead: no barrier over memory and no load; an op whose pairs are
 // all local needs neither.
-template <int T, bool IN_LDS, bool WAVE>
+template <int T, bool IN_LDS, bool WAVE, bool EVENTS>
 __device__ __forceinline__ void feedback_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
-                                            uint32_t code, uint64_t meas) {
+                                            uint32_t code, uint64_t meas, const uint64_t *ring, uint32_t ring_pos) {
   if (!(op.code & OPF_FB_LOCAL)) team_barrier_all<WAVE>();
   const uint32_t items = op.n * T;
   const uint32_t *tg = p.targets + op.toff;
@@ -417,9 +526,15 @@ __device__ __forceinline__ void feedback_op(const FrameParams &p, const Tile<T, 
     if (qw & TGT_FB_LOCAL) {
       f = tl.FX[ix];                            // this item's own cell
     } else {
-      const uint64_t m = meas - tg[2 * k + 1];
-      f = __hip_atomic_load(p.out + m * p.out_stride + tl.tw0 + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (p.ref != nullptr && ((p.ref[m >> 6] >> (m & 63)) & 1)) f = ~f;
+      const uint32_t back = tg[2 * k + 1];
+      if constexpr (EVENTS) {      // raw flips
+        f = __hip_atomic_load(ring + (size_t)ring_back(ring_pos, back, p.ring_rows) * T + j, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        const uint64_t m = meas - back;
+        f = __hip_atomic_load(p.out + m * p.out_stride + tl.tw0 + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p.ref != nullptr && ((p.ref[m >> 6] >> (m & 63)) & 1)) f = ~f;
+      }
     }
     if (code != OP_FB_Z) tl.FX[ix] ^= f;
     if (code != OP_FB_X) tl.FZ[ix] ^= f;
@@ -631,7 +746,7 @@ __device__ __forceinline__ uint2 load_meta(const uint32_t *w) {
 
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
 // LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
-template <int T, bool IN_LDS, bool WAVE = false>
+template <int T, bool IN_LDS, bool WAVE = false, bool EVENTS = false>
 __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, uint32_t slot, uint64_t *lds) {
   const uint32_t nwaves = WAVE ? 1u : blockDim.x >> 6;
   const uint32_t n = p.num_qubits;
@@ -652,6 +767,17 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   tl.valid = (int)((p.num_words - tl.tw0) < (uint64_t)T ? (p.num_words - tl.tw0) : (uint64_t)T);
 
   uint64_t flat = 0, meas = 0;
+  // EVENTS: ring of recent flips (detection events formed in the walk);
+  // ring_pos is the ring row of measurement `meas`, det the next detector.
+  uint64_t *ring = EVENTS ? p.ring + (size_t)slot * p.ring_rows * T : nullptr;
+  uint32_t ring_pos = 0, det = 0;
+  if (EVENTS && p.obs_out && p.num_obs) {
+    // Observable words start at zero; observable ops XOR into them atomically,
+    // after the full barrier below.
+    for (uint32_t i = team_tid<WAVE>(); i < p.num_obs * (uint32_t)T; i += team_size<WAVE>())
+      if ((int)(i % T) < tl.valid) p.obs_out[(size_t)(i / T) * p.out_stride + tl.tw0 + i % T] = 0;
+    team_barrier_all<WAVE>();
+  }
   uint32_t loop_left[8];
   int depth = 0;
   uint32_t noise_seq = 0;
@@ -704,6 +830,17 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       else depth--;
       continue;
     }
+    if constexpr (EVENTS) {      // event ops (only in the events program): no flat index, no barrier
+      if (code == OP_DET) {
+        detector_op<T, IN_LDS, WAVE>(p, tl, op, ring, ring_pos, det);
+        det += op.n;
+        continue;
+      }
+      if (code == OP_OBS) {
+        if (p.obs_out) observable_op<T, IN_LDS, WAVE>(p, tl, op, ring, ring_pos);
+        continue;
+      }
+    }
     uint64_t instr;
     if (code == OP_INIT) {
       instr = INIT_INSTRUCTION;
@@ -714,7 +851,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       instr = flat - 1;
     }
     if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
-      collapse_op<T, IN_LDS, WAVE>(p, tl, op, code, instr, meas, stage_b);
+      collapse_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, code, instr, meas, ring, ring_pos, stage_b);
     } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
       const uint32_t inst = noise_seq++;
       uint32_t count = kNoRecords;                 // same value in every thread
@@ -742,7 +879,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
         noise_op<T, IN_LDS, WAVE>(p, tl, op, code, instr, thr_lds);
       }
     } else if (code >= OP_FB_X) {
-      feedback_op<T, IN_LDS, WAVE>(p, tl, op, code, meas);
+      feedback_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, code, meas, ring, ring_pos);
     } else {
       switch (code) {
         case OP_SWAP_XZ: clifford_op<T, IN_LDS, WAVE, OP_SWAP_XZ>(p, tl, op, stage_b); break;
@@ -754,20 +891,27 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
         default: clifford_op<T, IN_LDS, WAVE, OP_SWAP>(p, tl, op, stage_b); break;
       }
     }
-    if (code == OP_M || code == OP_MR) meas += op.n;
-    team_barrier<IN_LDS, WAVE>();
+    if (code == OP_M || code == OP_MR) {
+      meas += op.n;
+      if constexpr (EVENTS)
+        ring_pos = ring_pos + op.n < p.ring_rows ? ring_pos + op.n : ring_pos + op.n - p.ring_rows;
+    }
+    // Flips in the ring are read back by other waves: a measurement's barrier
+    // then covers global memory too.
+    if (EVENTS && (code == OP_M || code == OP_MR)) team_barrier_all<WAVE>();
+    else team_barrier<IN_LDS, WAVE>();
   }
 }
 
 // One workgroup per tile, or (a global frame) a smaller grid of workgroups
 // that take tiles in turn, each reusing its own scratch slot, so that the
 // frames in flight stay within the caches.
-template <int T, bool IN_LDS>
+template <int T, bool IN_LDS, bool EVENTS>
 __global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
   extern __shared__ uint64_t lds[];
   const uint32_t ntiles = (uint32_t)((p.num_words + T - 1) / T);
   const uint32_t first = xcd_tile(blockIdx.x, gridDim.x);
-  for (uint32_t t = first; t < ntiles; t += gridDim.x) walk_tile<T, IN_LDS>(p, t, blockIdx.x, lds);
+  for (uint32_t t = first; t < ntiles; t += gridDim.x) walk_tile<T, IN_LDS, false, EVENTS>(p, t, blockIdx.x, lds);
 }
 
 // Persistent multi-circuit kernel: every workgroup pops (request, tile) items
@@ -901,9 +1045,15 @@ size_t frame_lds_bytes(uint64_t n, int T, bool in_lds, uint32_t threads) {
 template <int T, bool IN_LDS>
 static hipError_t launch_frame_t(const FrameParams &p, uint32_t tiles, uint32_t threads, size_t lds_bytes,
                                  hipStream_t stream) {
-  hipError_t e = allow_dynamic_lds((const void *)k_frame<T, IN_LDS>, (int)kMaxLdsBytes);
+  // One instantiation per mode, so that the measurement-mode walk carries
+  // none of the ring's state.
+  const void *k = p.ring ? (const void *)k_frame<T, IN_LDS, true> : (const void *)k_frame<T, IN_LDS, false>;
+  hipError_t e = allow_dynamic_lds(k, (int)kMaxLdsBytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_frame<T, IN_LDS>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
+  if (p.ring)
+    hipLaunchKernelGGL((k_frame<T, IN_LDS, true>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
+  else
+    hipLaunchKernelGGL((k_frame<T, IN_LDS, false>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
   return hipGetLastError();
 }
 
@@ -911,7 +1061,7 @@ hipError_t launch_frame(const FrameParams &p, const FrameConfig &cfg, hipStream_
   size_t lds = frame_lds_bytes(p.num_qubits, cfg.tile_words, cfg.in_lds, cfg.threads);
   if (lds > kMaxLdsBytes || cfg.threads % 64 || cfg.threads == 0 || cfg.threads > 1024) return hipErrorInvalidValue;
   uint32_t tiles = (uint32_t)((p.num_words + cfg.tile_words - 1) / cfg.tile_words);
-  if (!cfg.in_lds && cfg.slots && cfg.slots < tiles) tiles = cfg.slots;      // workgroups of a global frame
+  if (cfg.slots && cfg.slots < tiles) tiles = cfg.slots;      // workgroups of a global frame, or ring slots
 #define STIM_CASE(TT)                                                                        \
   case TT:                                                                                   \
     return cfg.in_lds ? launch_frame_t<TT, true>(p, tiles, cfg.threads, lds, stream)         \

@@ -1,7 +1,7 @@
 """GPU: stim_sample_scratch_bytes reports what a sampling call takes.
 
-The library allocates its per-call scratch (flip table, noise records and
-their tables, global frame slots) from the device's default stream-ordered
+The library allocates its per-call scratch (flip rings or flip table, noise
+records and their tables, global frame slots) from the device's default stream-ordered
 pool; all of it is live at once, so the pool's used-memory high-water mark
 over one call, minus what was in use before, is that scratch (allocations are
 rounded up by the pool, so a small slack per allocation is allowed).
@@ -42,14 +42,17 @@ def pool_attr(H, pool, attr):
     return v.value
 
 
-@pytest.mark.parametrize("d,p,shots,mode", [
-    (5, 1e-3, 65536, "frame"), (9, 1e-2, 100_000, "detector"), (25, 1e-3, 65536, "detector"),
-    (71, 1e-3, 8192, "frame"),                    # frame slice past LDS: global frame slots
+@pytest.mark.parametrize("d,p,shots,mode,walk_events", [
+    (5, 1e-3, 65536, "frame", "1"), (9, 1e-2, 100_000, "detector", "1"), (25, 1e-3, 65536, "detector", "1"),
+    (9, 1e-2, 100_000, "detector", "0"),          # flip table + event kernel
+    (71, 1e-3, 8192, "frame", "1"),               # frame slice past LDS: global frame slots
+    (71, 1e-3, 8192, "detector", "1"),            # global frame slots + flip rings
 ])
-def test_scratch_query_matches_pool_use(hip, d, p, shots, mode):
+def test_scratch_query_matches_pool_use(hip, d, p, shots, mode, walk_events, monkeypatch):
     from paper_2103_02202_amd import stim_gpu as sg
     H, pool = hip
-    announce("scratch", d, p, shots, mode)
+    monkeypatch.setenv("STIM_WALK_EVENTS", walk_events)
+    announce("scratch", d, p, shots, mode, walk_events)
     c = sg.Circuit(wl.surface_code(d, d, p))
     W = (shots + 63) // 64
     rows = c.num_measurements if mode == "frame" else c.num_detectors
