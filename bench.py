@@ -3,18 +3,20 @@ experiment (49 rounds, p = 1e-3, 65,536 shots) on one MI355X.
 
 One step = one pass of the whole sampling path over one batch of shots:
 frame initialisation, Clifford propagation, Pauli noise, resets, measurements
-and detection events + observable flips (stim_detector_sample: the frame
-kernel forms the events from a ring of its recent flips).  Inputs (the compiled program and reference sample)
+(flip record written to HBM) and detection events + observable flips
+(stim_detector_sample).  Inputs (the compiled program and reference sample)
 are resident on the GPU before the timed region; compile and reference
 ("analysis") time is reported separately.
 
 Prints one JSON line.  Fields beyond the driver's contract:
   roofline      -- for the step's frame kernel (k_frame, HIP events on its
-                   stream): compulsory bytes (the event tables it writes)
+                   stream): compulsory bytes (the flip record it writes)
                    against HBM peak, measured HBM traffic when the counters
                    match the sources
   cpu_baseline  -- the oracle (-O3 -march=native) timed on this host on a
                    bounded shot sample, at all usable CPUs and at one
+  walk_events   -- the same step with the events formed inside the frame
+                   walk (STIM_WALK_EVENTS=1) instead of the flip record
   configs       -- d=3 x 1,024, d=15 x 2^20 and d=49 x 262,144 shots:
                    detector- and measurement-mode call times
   analysis_s    -- host compile + reference-sample time
@@ -524,9 +526,9 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = G * SHOTS / (dt / args.steps)
 
-    # The step's kernels: the noise pre-pass and the frame kernel, which forms
-    # the detection events itself (HIP events recorded by the library on the
-    # stream the kernels run on).
+    # The step's kernels: the noise pre-pass and the frame kernel, which
+    # writes the flip record the event kernel then reads (HIP events recorded
+    # by the library on the stream the kernels run on).
     reps = max(5, args.steps)
     stim_gpu.stim_kernel_timing(True)
     for _ in range(reps):
@@ -553,14 +555,13 @@ def main():
     stim_gpu.stim_kernel_timing(False)
     pass_ms = ev0.elapsed_time(ev1) / reps
     gen_ms, kframe_ms = gen_ms / passes, kframe_ms / passes
-    # Dominant kernel: k_frame of the step (detector mode).  Its algorithmic
-    # bytes are the compulsory ones, the event and observable tables it writes
-    # ((D + L) S / 8 bytes: one bit per detector and shot; the frame stays on
-    # chip, the flip ring in the caches).
+    # Dominant kernel: k_frame of the step.  Its algorithmic bytes are the
+    # compulsory ones, the flip record it writes (M S / 8 bytes: one bit per
+    # measurement and shot; the frame stays on chip).
     event_bytes = (Dn + L) * SHOTS / 8
     record_bytes = M * SHOTS / 8
     per_op_bytes = streaming_bytes(D, ROUNDS, P, SHOTS)
-    achieved = event_bytes / (det_frame_ms * 1e-3) / 1e9
+    achieved = record_bytes / (det_frame_ms * 1e-3) / 1e9
     digest = sources_digest()
     fresh = PMC_KIB is not None and PMC_SOURCES == digest
     traffic = None
@@ -569,12 +570,11 @@ def main():
         traffic = 1024 * (f * FETCH_SCALE + w * WRITE_SCALE)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_frame (detector mode: events formed in the walk)",
-                "launch_ms": det_frame_ms, "algorithmic_bytes": event_bytes,
-                "algorithmic_bytes_basis": "compulsory: the event and observable tables, (D+L)*S/8 bytes "
-                                           "(frame kept in LDS)",
+                "kernel": "k_frame (the step's walk: flip record for the event kernel)",
+                "launch_ms": det_frame_ms, "algorithmic_bytes": record_bytes,
+                "algorithmic_bytes_basis": "compulsory: the flip record, M*S/8 bytes (frame kept in LDS)",
                 "measured_hbm_frac": (traffic / (det_frame_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                "traffic_over_algorithmic": (traffic / event_bytes) if traffic else None,
+                "traffic_over_algorithmic": (traffic / record_bytes) if traffic else None,
                 "per_op_streaming_bytes": per_op_bytes,
                 "traffic_over_per_op_streaming": (traffic / per_op_bytes) if traffic else None,
                 "k_noise_gen_ms": det_gen_ms,
@@ -603,6 +603,13 @@ def main():
                       "k_frame_record_GBs": record_bytes / (kframe_ms * 1e-3) / 1e9},
         "analysis_s": {"compile": compile_s, "reference": ref_s},
     }
+    # The alternative detector path: events formed inside the walk from flip
+    # rings (STIM_WALK_EVENTS=1), the same bits without the flip record.
+    os.environ["STIM_WALK_EVENTS"] = "1"
+    walk_ms = time_calls(step, max(3, args.steps // 2), stream)
+    del os.environ["STIM_WALK_EVENTS"]
+    out["walk_events"] = {"ms": walk_ms, "flip_record_ms": ms_per_step,
+                          "event_bytes": event_bytes, "note": "STIM_WALK_EVENTS=1 path, not the default"}
     out["host_copy"] = bench_host_copy(det, obs, stream, ms_per_step, G)
     if not args.no_formats:
         out["formats"] = bench_formats(det, meas, Dn, M, SHOTS)

@@ -113,12 +113,12 @@ int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint
  * out_det: device [num_detectors][W]; out_obs: device [num_observables][W] or
  * NULL.  Event = XOR of the detector's measurement flips (the reference bits
  * cancel because detectors are deterministic in the noiseless circuit).
- * The frame walk forms the events itself from a per-workgroup ring of its
- * recent flips (longest detector, observable or feedback lookback plus the
- * largest measurement instruction, at most the whole record, in rows of the
- * tile's words) when those
- * rings fit in 512 MiB; otherwise (or with STIM_WALK_EVENTS=0) it writes the
- * flip record and a second kernel forms the events.  Same bits either way. */
+ * The frame walk writes the flip record and a second kernel forms the
+ * events.  With STIM_WALK_EVENTS=1 the walk forms the events itself from a
+ * per-workgroup ring of its recent flips (longest detector, observable or
+ * feedback lookback plus the largest measurement instruction, at most the
+ * whole record, in rows of the tile's words) when those rings fit in 512 MiB.
+ * Same bits either way. */
 int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
                          uint64_t *out_det, uint64_t *out_obs, void *hip_stream);
 

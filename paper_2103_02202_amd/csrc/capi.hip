@@ -526,16 +526,18 @@ uint64_t pass_scratch_bytes(const Program &P, uint64_t num_shots, int dev) {
   return bytes;
 }
 
-// Detection events formed in the walk (Sec. 5.6): each workgroup keeps its
-// recent flips in a ring of max_lookback + max_measure_op rows (at most the
-// record's length) of T words, and
-// detector and observable ops write the event tables directly, so the flip
-// record is never written out and read back.  Rings are per workgroup slot:
-// one workgroup per tile for an LDS-resident frame (capped by a memory
-// budget, beyond which workgroups take several tiles in turn), the global
-// frame's slots otherwise.  Off (flip record + event kernel) when
-// STIM_WALK_EVENTS=0, or when the rings would exceed the budget;
-// STIM_WALK_EVENT_SLOTS caps the slots (workgroups then take tiles in turn).
+// Detection events formed in the walk (Sec. 5.6), on request
+// (STIM_WALK_EVENTS=1): each workgroup keeps its recent flips in a ring of
+// max_lookback + max_measure_op rows (at most the record's length) of T
+// words, and detector and observable ops write the event tables directly, so
+// the flip record is never written out and read back.  Rings are per
+// workgroup slot: one workgroup per tile for an LDS-resident frame (capped by
+// a memory budget, beyond which workgroups take several tiles in turn), the
+// global frame's slots otherwise.  Not the default: the rings live in global
+// memory (the LDS holds the frame), and on surface codes from d = 3 to 49
+// their traffic through L2 cost the walk as much as the event kernel it
+// saves, or more.  STIM_WALK_EVENT_SLOTS caps the slots (workgroups then take
+// tiles in turn).
 constexpr uint64_t kRingBudget = 512ull << 20;
 
 struct WalkEvents {
@@ -552,7 +554,7 @@ uint32_t ring_rows(const Program &P) {
 // Ring slots of a walk with events for num_shots shots (0: not possible).
 uint64_t walk_event_slots(const Program &P, uint64_t num_shots, int dev) {
   const char *env = std::getenv("STIM_WALK_EVENTS");
-  if (env && std::strcmp(env, "0") == 0) return 0;
+  if (!env || std::strcmp(env, "1") != 0) return 0;
   if (P.num_detectors + P.num_observables == 0) return 0;
   if ((uint64_t)P.max_lookback + P.max_measure_op >= (1ull << 31)) return 0;
   const uint64_t W = (num_shots + 63) / 64;

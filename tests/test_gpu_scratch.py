@@ -43,9 +43,9 @@ def pool_attr(H, pool, attr):
 
 
 @pytest.mark.parametrize("d,p,shots,mode,walk_events", [
-    (5, 1e-3, 65536, "frame", "1"), (9, 1e-2, 100_000, "detector", "1"), (25, 1e-3, 65536, "detector", "1"),
-    (9, 1e-2, 100_000, "detector", "0"),          # flip table + event kernel
-    (71, 1e-3, 8192, "frame", "1"),               # frame slice past LDS: global frame slots
+    (5, 1e-3, 65536, "frame", "0"), (9, 1e-2, 100_000, "detector", "0"), (25, 1e-3, 65536, "detector", "0"),
+    (9, 1e-2, 100_000, "detector", "1"),          # flip rings of events formed in the walk
+    (71, 1e-3, 8192, "frame", "0"),               # frame slice past LDS: global frame slots
     (71, 1e-3, 8192, "detector", "1"),            # global frame slots + flip rings
 ])
 def test_scratch_query_matches_pool_use(hip, d, p, shots, mode, walk_events, monkeypatch):

@@ -1,7 +1,7 @@
-"""Detection events formed inside the frame walk (the walk keeps its recent
-measurement flips in a per-workgroup ring and writes event and observable rows
-itself), against the oracle bit for bit, and against the flip-record path
-(STIM_WALK_EVENTS=0: flip record written out, events formed by a second
+"""Detection events formed inside the frame walk (STIM_WALK_EVENTS=1: the walk
+keeps its recent measurement flips in a per-workgroup ring and writes event
+and observable rows itself), against the oracle bit for bit, and against the
+default flip-record path (flip record written out, events formed by a second
 kernel).
 
 The circuits put detectors of 0 to 5 lookbacks (repeats and empty detectors
@@ -26,6 +26,11 @@ torch = pytest.importorskip("torch")
 def announce(*a):
     print("[case]", *a, flush=True)
     sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def walk_events(monkeypatch):
+    monkeypatch.setenv("STIM_WALK_EVENTS", "1")
 
 
 @pytest.fixture(scope="module")
@@ -95,12 +100,11 @@ def test_flip_record_path_gives_the_same_bits(sg, monkeypatch):
     for i, (text, seed, shots, off) in enumerate(cases):
         announce("walk events vs flip record", i)
         c = sg.Circuit(text)
-        monkeypatch.delenv("STIM_WALK_EVENTS", raising=False)
+        monkeypatch.setenv("STIM_WALK_EVENTS", "1")
         a = gpu_events(c, seed, shots, off)
         monkeypatch.setenv("STIM_WALK_EVENTS", "0")
         b = gpu_events(c, seed, shots, off)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), f"case {i}"
-    monkeypatch.delenv("STIM_WALK_EVENTS", raising=False)
 
 
 def test_observables_not_requested_and_detector_only(sg):
