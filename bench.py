@@ -57,9 +57,13 @@ HBM_PEAK_GBS = 8000.0
 # written.  The counters hold for the library sources whose digest is
 # PMC_SOURCES; once any of them changes, `traffic` is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-PMC_KIB = None                 # {"k_frame": (FETCH_SIZE KiB, WRITE_SIZE KiB)}
-PMC_SOURCES = None             # sources_digest() when the counters were taken
+PMC_KIB = {"k_frame": (360572.4, 989671.6)}     # FETCH_SIZE KiB, WRITE_SIZE KiB per dispatch
+# SQ counters of the same kernel and workload (per dispatch): what bounds it.
+PMC_SQ = {"SQ_INSTS_VALU": 1.027e9, "SQ_BUSY_CU_CYCLES": 1.718e9, "SQ_LDS_IDX_ACTIVE": 4.382e8,
+          "SQ_LDS_BANK_CONFLICT": 1.959e8, "SQ_WAIT_ANY": 2.951e9, "SQ_WAVE_CYCLES": 6.871e9}
+PMC_SOURCES = "f5ac1ae38842da25"                  # sources_digest() when the counters were taken
 PMC_PROFILE = "profiles/k_frame_surface_d49_65536shots.md"
+CUS, CLOCK_HZ = 256, 2.4e9
 
 
 def sources_digest() -> str:
@@ -579,6 +583,20 @@ def main():
                 "traffic_over_per_op_streaming": (traffic / per_op_bytes) if traffic else None,
                 "k_noise_gen_ms": det_gen_ms,
                 "counters": PMC_PROFILE if fresh else f"none for library sources {digest}"}
+    if fresh:
+        # The resource that binds the kernel, from its counters against this
+        # run's launch time: VALU issue (one wave64 instruction per CU and
+        # cycle), the LDS pipe's active cycles (and the share of them lost to
+        # bank conflicts), and the waves' waiting time.  None is saturated:
+        # the walk is bound by issue and barrier latency.
+        cu_cycles = CUS * CLOCK_HZ * det_frame_ms * 1e-3
+        roofline["binding_resource"] = {
+            "name": "VALU issue and barrier latency (no unit saturated)",
+            "valu_issue_frac": PMC_SQ["SQ_INSTS_VALU"] / cu_cycles,
+            "lds_active_frac": PMC_SQ["SQ_LDS_IDX_ACTIVE"] / cu_cycles,
+            "lds_bank_conflict_share": PMC_SQ["SQ_LDS_BANK_CONFLICT"] / PMC_SQ["SQ_LDS_IDX_ACTIVE"],
+            "wave_wait_frac": PMC_SQ["SQ_WAIT_ANY"] / PMC_SQ["SQ_WAVE_CYCLES"],
+            "hbm_measured_frac": roofline["measured_hbm_frac"]}
 
     out = {
         "metric": "shot-gates/s + HBM GB/s frac of peak; batched/served vs single; p99 latency",
