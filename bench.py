@@ -628,23 +628,29 @@ def main():
     del os.environ["STIM_WALK_EVENTS"]
     out["walk_events"] = {"ms": walk_ms, "flip_record_ms": ms_per_step,
                           "event_bytes": event_bytes, "note": "STIM_WALK_EVENTS=1 path, not the default"}
-    out["host_copy"] = bench_host_copy(det, obs, stream, ms_per_step, G)
+    def leg(name, fn):
+        # One progress line per leg on stderr; the result line stays on stdout.
+        t = time.perf_counter()
+        out[name] = fn()
+        print(json.dumps({"bench_leg": name, "s": round(time.perf_counter() - t, 1)}), file=sys.stderr, flush=True)
+
+    leg("host_copy", lambda: bench_host_copy(det, obs, stream, ms_per_step, G))
     if not args.no_formats:
-        out["formats"] = bench_formats(det, meas, Dn, M, SHOTS)
+        leg("formats", lambda: bench_formats(det, meas, Dn, M, SHOTS))
     if not args.no_feedback:
-        out["feedback"] = bench_feedback(max(3, args.steps // 2), det, obs, stream)
+        leg("feedback", lambda: bench_feedback(max(3, args.steps // 2), det, obs, stream))
     if not args.no_sparse:
-        out["sparse"] = bench_sparse(max(3, args.steps // 2), det, obs, stream)
+        leg("sparse", lambda: bench_sparse(max(3, args.steps // 2), det, obs, stream))
     if not args.no_configs:
-        out["configs"] = bench_configs(stream)
+        leg("configs", lambda: bench_configs(stream))
     if not args.no_reference:
-        out["reference"] = bench_reference()
+        leg("reference", bench_reference)
     if not args.no_batch:
-        out["batch"] = bench_batch(max(3, args.steps // 2))
+        leg("batch", lambda: bench_batch(max(3, args.steps // 2)))
     if not args.no_serving:
-        out["serving"] = bench_serving()
+        leg("serving", bench_serving)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(text, G)
+        leg("cpu_baseline", lambda: cpu_baseline(text, G))
     print(json.dumps(out), flush=True)
 
 
