@@ -33,9 +33,10 @@ Prints one JSON line.  Fields beyond the driver's contract:
                    inverse tableau vs the GPU tableau
   batch         -- the 64-circuit mix in one persistent graph-captured launch
                    vs the same requests one at a time
-  serving       -- Poisson request streams over the resident d = 3..101 pool:
-                   throughput and p50/p99 latency, continuous batching vs a
-                   one-at-a-time server
+  serving       -- Poisson request streams over the resident d = 3..101 pool,
+                   and over a pool of small codes (d = 3..15) at 3,000 and
+                   10,000 requests/s: throughput and p50/p99 latency,
+                   continuous batching vs a one-at-a-time server
 """
 from __future__ import annotations
 
@@ -423,6 +424,27 @@ def bench_serving(rates=(10, 30, 100, 300, 1000)):
     st = small.serve(workloads.serving_requests(60, rate=100.0, pool_size=len(pool), seed=100))
     out["budget_8GiB_rate_100"] = st
     print(json.dumps({"serving_budget_8GiB": {k: st[k] for k in keys}}), file=sys.stderr, flush=True)
+    # Many small requests: a pool of small surface codes (d = 3..15) at high
+    # rates, where one launch per request is bound by launch and wait
+    # overheads and continuous batching groups the arrivals.
+    spec = workloads.serving_pool(seed=1, d_max=15)
+    small_pool = serve.load_pool([x["text"] for x in spec], names=[f"d{x['d']}" for x in spec], threads=16)
+    small_srv = serve.Server(small_pool, hbm_budget_bytes=96 << 30, num_slots=4, max_chunk_shots=1 << 18,
+                             max_chunk_bytes=8 << 30)
+    small_srv.serve(workloads.serving_requests(16, rate=1000.0, pool_size=len(small_pool), seed=999,
+                                               max_shots=4096))                    # warm-up
+    out["small_pool"] = {"pool": "rotated surface codes d=3..15 (odd), rounds=d, p log-uniform [1e-4, 1e-2]",
+                         "requests": 400, "rates": {}}
+    for rate, max_shots in ((3000, 1 << 16), (10000, 1 << 12), (10000, 1 << 16)):
+        def reqs():
+            return workloads.serving_requests(400, rate=float(rate), pool_size=len(small_pool), seed=rate,
+                                              max_shots=max_shots)
+        a = small_srv.serve(reqs())
+        b = small_srv.serve_one_at_a_time(reqs())
+        out["small_pool"]["rates"][f"{rate}/shots<={max_shots}"] = {"continuous": a, "one_at_a_time": b}
+        print(json.dumps({"serving_small_pool": rate, "max_shots": max_shots,
+                          "continuous": {k: a[k] for k in keys}, "one_at_a_time": {k: b[k] for k in keys}}),
+              file=sys.stderr, flush=True)
     del os.environ["STIM_TUNE"]
     return out
 
