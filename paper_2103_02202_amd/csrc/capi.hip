@@ -48,6 +48,12 @@ int hip_error(hipError_t e, const char *what) {
 struct DeviceCopy {
   DevOp *ops = nullptr;
   DevOp *event_ops = nullptr;       // the program with event ops
+  // Detector mode of a circuit whose detectors and observables are all
+  // deterministic: the program with every collapse's Z randomisation marked
+  // unread (see ensure_noz_program); NULL when not built or not applicable.
+  DevOp *noz_ops = nullptr;
+  uint32_t *noz_targets = nullptr;
+  bool noz_checked = false;
   uint32_t *targets = nullptr;
   uint64_t *thresholds = nullptr;
   uint64_t *ref = nullptr;
@@ -183,7 +189,7 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
 
 void plan_window(stim_circuit *c);
 
-int ensure_error_model(stim_circuit *c) {
+void build_error_model_once(stim_circuit *c) {
   if (!c->have_em) {
     c->have_em = true;
     try {
@@ -206,7 +212,52 @@ int ensure_error_model(stim_circuit *c) {
       c->em_msg = std::string("building the error sets failed: ") + e.what();
     }
   }
+}
+
+int ensure_error_model(stim_circuit *c) {
+  build_error_model_once(c);
   return c->em_code ? set_error(c->em_code, c->em_msg) : STIM_OK;
+}
+
+// Detection events without the collapses' Z randomisations (Sec. 3, 5.6).
+// The frame is linear over GF(2) in its random bits, so the Z randomisation
+// drawn after a collapse adds to the events exactly the detector set of a Z
+// error at that point.  When every detector and observable is deterministic
+// -- the condition the error-set walk checks: no output is sensitive to an X
+// component on a qubit right after its collapse -- all those sets are empty,
+// and a detector-mode walk may skip every such draw: the events are the same
+// bits, only the intermediate flips of random measurements differ.  Built
+// once per device, with the caller holding c->mu; not for circuits the walk
+// refuses (random outputs, classically controlled Paulis, circuits too long
+// to walk), nor with STIM_EVENT_ZRAND=1.
+int ensure_noz_program(stim_circuit *c, DeviceCopy *d, hipStream_t s) {
+  if (d->noz_checked) return STIM_OK;
+  const char *env = std::getenv("STIM_EVENT_ZRAND");
+  if (env && std::strcmp(env, "1") == 0) return STIM_OK;     // not recorded: the switch may change
+  d->noz_checked = true;
+  const Program &P = c->prog;
+  if (P.num_detectors + P.num_observables == 0) return STIM_OK;
+  build_error_model_once(c);
+  if (c->em_code) return STIM_OK;
+  std::vector<DevOp> ops = P.ops;
+  std::vector<uint32_t> tg = P.targets;
+  for (DevOp &op : ops) {
+    const uint32_t code = op.code & 0xFFFFu;
+    if (code != OP_INIT && code != OP_R && code != OP_M && code != OP_MR) continue;
+    op.code &= ~OPF_ZRAND_LIVE;
+    for (uint32_t k = 0; k < op.n; k++) tg[(size_t)op.toff + k] |= TGT_DEAD_ZRAND;
+  }
+  hipError_t e;
+  DevOp *dops = nullptr;
+  uint32_t *dtg = nullptr;
+  if ((e = upload(ops, &dops, s)) != hipSuccess || (e = upload(tg, &dtg, s)) != hipSuccess) {
+    if (dops) (void)hipFree(dops);
+    return e == hipErrorOutOfMemory ? set_error(STIM_E_OOM, "device allocation failed") : hip_error(e, "upload");
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  d->noz_ops = dops;
+  d->noz_targets = dtg;
+  return STIM_OK;
 }
 
 // Plans the windowed sparse kernel: batches of consecutive noise executions
@@ -582,14 +633,17 @@ uint64_t walk_event_bytes(const Program &P, uint64_t num_shots, int dev) {
 // Runs the frame kernel; ref == nullptr writes raw flips.  With `ev`, the walk
 // forms detection events and observables instead of writing `out`.
 int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offset, uint64_t num_shots,
-              const uint64_t *ref, uint64_t *out, hipStream_t s, const WalkEvents *ev = nullptr) {
+              const uint64_t *ref, uint64_t *out, hipStream_t s, const WalkEvents *ev = nullptr,
+              bool noz = false) {
   const uint64_t W = (num_shots + 63) / 64;
   FrameConfig cfg = choose_config(c->prog.num_qubits, W);
   FrameParams p{};
-  p.ops = d->ops;
+  // noz: the detector-mode program without Z randomisations (same op list).
+  const bool use_noz = noz && d->noz_ops != nullptr;
+  p.ops = use_noz ? d->noz_ops : d->ops;
   p.num_ops = (uint32_t)c->prog.ops.size();
   p.num_qubits = (uint32_t)c->prog.num_qubits;
-  p.targets = d->targets;
+  p.targets = use_noz ? d->noz_targets : d->targets;
   p.thresholds = d->thresholds;
   p.ref = ref;
   p.seed = seed;
@@ -1050,6 +1104,10 @@ void batch_params(BatchPlan &pl, std::vector<FrameParams> &params, uint64_t *fli
       off += std::max<uint64_t>(r.c->prog.num_measurements, 1) * W;
       p.ref = nullptr;
       p.out = pl.flips[i];
+      if (d.noz_ops) {           // the program without Z randomisations (same events)
+        p.ops = d.noz_ops;
+        p.targets = d.noz_targets;
+      }
     } else {
       p.ref = d.ref;
       p.out = r.out0;
@@ -1322,7 +1380,7 @@ void stim_circuit_free(stim_circuit *c) {
   for (auto &kv : c->dev) {
     (void)hipSetDevice(kv.first);
     DeviceCopy &d = kv.second;
-    void *ptrs[] = {d.ops,       d.event_ops,   d.targets,     d.thresholds, d.ref,     d.det_off,
+    void *ptrs[] = {d.ops,       d.event_ops,   d.noz_ops,     d.noz_targets, d.targets,     d.thresholds, d.ref,     d.det_off,
                     d.det_idx,   d.obs_off,     d.obs_idx,    d.det_order, d.noise_pc,
                     d.noise_instr, d.gen_base, d.set_off,    d.set_lanes, d.wb_e0,
                     d.wb_e1,       d.wb_base};
@@ -1382,6 +1440,7 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
     std::lock_guard<std::mutex> lock(c->mu);
     if ((rc = ensure_reference(c, s, true))) return rc;
     if ((rc = ensure_device(c, s, &d))) return rc;
+    if ((rc = ensure_noz_program(c, d, s))) return rc;
   }
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -1397,7 +1456,7 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   size_t bytes = (size_t)std::max<uint64_t>(c->prog.num_measurements, 1) * W * sizeof(uint64_t);
   hipError_t e = hipMallocAsync((void **)&flips, bytes, s);
   if (e != hipSuccess) return set_error(STIM_E_OOM, "flip scratch allocation failed");
-  rc = run_frame(c, d, seed, shot_offset, num_shots, nullptr, flips, s);
+  rc = run_frame(c, d, seed, shot_offset, num_shots, nullptr, flips, s, nullptr, true);
   if (!rc && (e = launch_parity(flips, W, d->det_off, d->det_idx, d->det_order, (uint32_t)c->prog.num_detectors,
                                 out_det, s)) != hipSuccess)
     rc = hip_error(e, "detector kernel launch");
@@ -1423,6 +1482,8 @@ int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_o
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
   DeviceCopy *d = nullptr;
+  const DevOp *ops = nullptr;
+  const uint32_t *targets = nullptr;
   {
     std::lock_guard<std::mutex> lock(c->mu);
     auto it = c->dev.find(dev);
@@ -1430,6 +1491,10 @@ int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_o
       return set_error(STIM_E_INVALID_ARG, "the circuit is not resident on device " + std::to_string(dev) +
                                                ": an allocating sampling call on this device uploads it first");
     d = &it->second;
+    // The program without Z randomisations if an earlier detector call built
+    // it (this entry point allocates nothing, so it never builds it).
+    ops = d->noz_ops ? d->noz_ops : d->ops;
+    targets = d->noz_ops ? d->noz_targets : d->targets;
   }
   const Program &P = c->prog;
   const uint64_t W = (num_shots + 63) / 64;
@@ -1450,10 +1515,10 @@ int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_o
   if ((rc = noalloc_scratch(dev, &base))) return rc;
   uint64_t *flips = (uint64_t *)base;
   FrameParams p{};
-  p.ops = d->ops;
+  p.ops = ops;
   p.num_ops = (uint32_t)P.ops.size();
   p.num_qubits = (uint32_t)P.num_qubits;
-  p.targets = d->targets;
+  p.targets = targets;
   p.thresholds = d->thresholds;
   p.ref = nullptr;                         // raw flips
   p.seed = seed;
@@ -1717,6 +1782,7 @@ int stim_batch_sample(const stim_request *reqs, size_t n, void *hip_stream) {
     DeviceCopy *d = nullptr;
     if ((rc = ensure_reference(r.c))) return rc;
     if ((rc = ensure_device(r.c, s, &d))) return rc;
+    if (r.mode == 1 && (rc = ensure_noz_program(r.c, d, s))) return rc;
   }
   std::lock_guard<std::mutex> lock(g_batch_mu);
   BatchPlan *plan = nullptr;
