@@ -155,6 +155,19 @@ def cpu_baseline(text: str, num_gate_targets: int, budget_s: float = 10.0):
             "build": "g++ -std=c++17 -O3 -march=native -fopenmp", "host": cpu, "reference_s": ref_s}
 
 
+def finite(x):
+    """x with every non-finite float replaced by None: the result line is
+    strict JSON (no NaN or Infinity)."""
+    import math
+    if isinstance(x, float):
+        return x if math.isfinite(x) else None
+    if isinstance(x, dict):
+        return {k: finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite(v) for v in x]
+    return x
+
+
 def time_calls(fn, reps, stream):
     """Average milliseconds per call of fn() over `reps` calls, HIP events on
     the stream the calls enqueue on (after two warm-up calls)."""
@@ -673,7 +686,7 @@ def main():
         leg("serving", bench_serving)
     if not args.no_cpu_baseline:
         leg("cpu_baseline", lambda: cpu_baseline(text, G))
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

@@ -71,8 +71,9 @@ def load_pool(texts, names=None, threads: int = 8):
 
 
 def percentile(values, q):
+    """The q-th percentile (linear interpolation), or None for no values."""
     if not values:
-        return float("nan")
+        return None
     v = sorted(values)
     k = (len(v) - 1) * q / 100.0
     lo, hi = int(math.floor(k)), int(math.ceil(k))
@@ -317,15 +318,20 @@ class Server:
         small = [r["completion"] - r["arrival"] for r in reqs if "completion" in r and work[id(r)] < self.SMALL_WORK]
         large = [r["completion"] - r["arrival"] for r in reqs if "completion" in r and work[id(r)] >= self.SMALL_WORK]
         frame_sg = sum(work[id(r)] for r in reqs if self.pool[r["circuit"]].method == "frame")
+
+        def ms(values, q):       # None (JSON null) when there is no such request
+            v = percentile(values, q)
+            return None if v is None else 1e3 * v
+
         return {"requests": len(reqs), "shot_gates": sg, "makespan_s": stats["makespan_s"],
                 "equivalent_shot_gates_per_s": sg / stats["makespan_s"],
                 "frame_path_shot_gates": frame_sg,
                 "requests_per_s": len(reqs) / stats["makespan_s"],
-                "p50_latency_ms": 1e3 * percentile(lat, 50), "p99_latency_ms": 1e3 * percentile(lat, 99),
+                "p50_latency_ms": ms(lat, 50), "p99_latency_ms": ms(lat, 99),
                 "mean_latency_ms": 1e3 * sum(lat) / max(len(lat), 1),
-                "small_requests": len(small), "small_p50_latency_ms": 1e3 * percentile(small, 50),
-                "small_p99_latency_ms": 1e3 * percentile(small, 99),
-                "large_p50_latency_ms": 1e3 * percentile(large, 50),
-                "large_p99_latency_ms": 1e3 * percentile(large, 99),
+                "small_requests": len(small), "small_p50_latency_ms": ms(small, 50),
+                "small_p99_latency_ms": ms(small, 99),
+                "large_p50_latency_ms": ms(large, 50),
+                "large_p99_latency_ms": ms(large, 99),
                 "deferrals": stats["deferrals"],
                 "launches": stats["launches"], "chunks": stats["chunks"], "max_group": stats["max_group"]}
