@@ -58,6 +58,7 @@ struct DeviceCopy {
   uint64_t *thresholds = nullptr;
   uint64_t *ref = nullptr;
   uint32_t *det_off = nullptr, *det_idx = nullptr, *obs_off = nullptr, *obs_idx = nullptr, *det_order = nullptr;
+  uint32_t *det_blocks = nullptr;   // Program::det_blocks
   uint32_t *noise_pc = nullptr;
   uint64_t *noise_instr = nullptr;
   // Error sets of sparse detection sampling (uploaded on its first use).
@@ -174,6 +175,7 @@ int ensure_device(stim_circuit *c, hipStream_t s, DeviceCopy **out) {
       (e = upload(P.det_offsets, &d.det_off, s)) != hipSuccess ||
       (e = upload(P.det_indices, &d.det_idx, s)) != hipSuccess ||
       (e = upload(P.det_order, &d.det_order, s)) != hipSuccess ||
+      (e = upload(P.det_blocks, &d.det_blocks, s)) != hipSuccess ||
       (e = upload(P.obs_offsets, &d.obs_off, s)) != hipSuccess ||
       (e = upload(P.obs_indices, &d.obs_idx, s)) != hipSuccess ||
       (e = upload(P.noise_pc, &d.noise_pc, s)) != hipSuccess ||
@@ -1067,8 +1069,8 @@ hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
     if (r.mode != 1) continue;
     DeviceCopy &d = r.c->dev[pl.device];
     const uint64_t W = (r.num_shots + 63) / 64;
-    e = launch_parity(pl.flips[i], W, d.det_off, d.det_idx, d.det_order, (uint32_t)r.c->prog.num_detectors,
-                      r.out0, s);
+    e = launch_parity_blocks(pl.flips[i], W, d.det_blocks, r.c->prog.det_blocks.size() / kDetBlockWords, d.det_off,
+                             d.det_idx, r.out0, s);
     if (e == hipSuccess && r.out1)
       e = launch_parity(pl.flips[i], W, d.obs_off, d.obs_idx, nullptr, (uint32_t)r.c->prog.num_observables, r.out1,
                         s);
@@ -1381,7 +1383,7 @@ void stim_circuit_free(stim_circuit *c) {
     (void)hipSetDevice(kv.first);
     DeviceCopy &d = kv.second;
     void *ptrs[] = {d.ops,       d.event_ops,   d.noz_ops,     d.noz_targets, d.targets,     d.thresholds, d.ref,     d.det_off,
-                    d.det_idx,   d.obs_off,     d.obs_idx,    d.det_order, d.noise_pc,
+                    d.det_idx,   d.obs_off,     d.obs_idx,    d.det_order, d.det_blocks, d.noise_pc,
                     d.noise_instr, d.gen_base, d.set_off,    d.set_lanes, d.wb_e0,
                     d.wb_e1,       d.wb_base};
     for (void *p : ptrs) if (p) (void)hipFree(p);
@@ -1457,8 +1459,8 @@ int stim_detector_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, u
   hipError_t e = hipMallocAsync((void **)&flips, bytes, s);
   if (e != hipSuccess) return set_error(STIM_E_OOM, "flip scratch allocation failed");
   rc = run_frame(c, d, seed, shot_offset, num_shots, nullptr, flips, s, nullptr, true);
-  if (!rc && (e = launch_parity(flips, W, d->det_off, d->det_idx, d->det_order, (uint32_t)c->prog.num_detectors,
-                                out_det, s)) != hipSuccess)
+  if (!rc && (e = launch_parity_blocks(flips, W, d->det_blocks, c->prog.det_blocks.size() / kDetBlockWords, d->det_off,
+                                      d->det_idx, out_det, s)) != hipSuccess)
     rc = hip_error(e, "detector kernel launch");
   if (!rc && out_obs &&
       (e = launch_parity(flips, W, d->obs_off, d->obs_idx, nullptr, (uint32_t)c->prog.num_observables, out_obs, s)) !=
@@ -1533,7 +1535,8 @@ int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_o
   if (P.num_measurements > 0 || P.num_qubits > 0) {
     if ((e = launch_frame(p, cfg, s)) != hipSuccess) return hip_error(e, "frame kernel launch");
   }
-  if ((e = launch_parity(flips, W, d->det_off, d->det_idx, d->det_order, (uint32_t)P.num_detectors, out_det, s)) !=
+  if ((e = launch_parity_blocks(flips, W, d->det_blocks, P.det_blocks.size() / kDetBlockWords, d->det_off, d->det_idx,
+                                out_det, s)) !=
       hipSuccess)
     return hip_error(e, "detector kernel launch");
   if (out_obs &&

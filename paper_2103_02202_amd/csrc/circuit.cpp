@@ -11,6 +11,7 @@
 // running counter and the per-op `lead` (lines skipped since the previous op).
 #include "circuit.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -676,6 +677,61 @@ Program compile_program(const std::vector<Node> &tree) {
       else all_local = false;
     }
     if (all_local && op.n > 0) op.code |= OPF_FB_LOCAL;
+  }
+  // Detector blocks for the event kernel, cut greedily along det_order.
+  {
+    Program &P = L.prog;
+    const size_t D = P.det_order.size();
+    std::vector<uint32_t> rows, dets, masks;
+    auto emit = [&]() {
+      if (dets.empty()) return;
+      const size_t b = P.det_blocks.size();
+      P.det_blocks.resize(b + kDetBlockWords, 0);
+      uint32_t *w = &P.det_blocks[b];
+      w[0] = (uint32_t)dets.size() | (uint32_t)rows.size() << 8;
+      for (size_t r = 0; r < rows.size(); r++) w[1 + r] = rows[r];
+      for (size_t i = 0; i < dets.size(); i++) {
+        w[1 + kDetBlockRows + i] = dets[i];
+        w[1 + kDetBlockRows + kDetBlockDets + i] = masks[i];
+      }
+      rows.clear();
+      dets.clear();
+      masks.clear();
+    };
+    for (size_t i = 0; i < D; i++) {
+      const uint32_t d = P.det_order[i];
+      const uint32_t a0 = P.det_offsets[d], a1 = P.det_offsets[d + 1];
+      // Rows this detector adds to the current block.
+      std::vector<uint32_t> extra;
+      for (uint32_t a = a0; a < a1; a++) {
+        const uint32_t m = P.det_indices[a];
+        if (std::find(rows.begin(), rows.end(), m) == rows.end() &&
+            std::find(extra.begin(), extra.end(), m) == extra.end())
+          extra.push_back(m);
+      }
+      if (dets.size() == kDetBlockDets || rows.size() + extra.size() > kDetBlockRows) {
+        emit();
+        extra.clear();
+        for (uint32_t a = a0; a < a1; a++) {
+          const uint32_t m = P.det_indices[a];
+          if (std::find(extra.begin(), extra.end(), m) == extra.end()) extra.push_back(m);
+        }
+      }
+      if (extra.size() > kDetBlockRows) {          // one detector with many rows: CSR block
+        const size_t b = P.det_blocks.size();
+        P.det_blocks.resize(b + kDetBlockWords, 0);
+        P.det_blocks[b] = 1u | kDetBlockCsr;
+        P.det_blocks[b + 1] = d;
+        continue;
+      }
+      rows.insert(rows.end(), extra.begin(), extra.end());
+      uint32_t mask = 0;
+      for (uint32_t a = a0; a < a1; a++)
+        mask ^= 1u << (uint32_t)(std::find(rows.begin(), rows.end(), P.det_indices[a]) - rows.begin());
+      dets.push_back(d);
+      masks.push_back(mask);
+    }
+    emit();
   }
   // Split off the event ops: `ops` keeps everything else, with loop targets
   // renumbered.

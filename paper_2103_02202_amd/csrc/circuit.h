@@ -110,6 +110,9 @@ struct Program {
   // that share a measurement (each continues from the latest measurement of
   // the previous one), so that a shared flip row is loaded once.
   std::vector<uint32_t> det_order;
+  // The same order cut into blocks for the event kernel, kDetBlockWords words
+  // each: see DetBlock below.
+  std::vector<uint32_t> det_blocks;
   uint64_t num_qubits = 0, num_measurements = 0, num_detectors = 0, num_observables = 0;
   uint64_t num_gate_targets = 0, num_noise_targets = 0, num_instructions = 0;
   uint32_t max_loop_depth = 0;
@@ -122,6 +125,17 @@ struct Program {
   std::vector<uint32_t> noise_pc;
   std::vector<uint64_t> noise_instr;
 };
+
+// A block of consecutive detectors (in det_order) that together read at most
+// kDetBlockRows distinct flip rows, at most kDetBlockDets of them:
+//   word 0: detectors | rows << 8 | (1 << 31 when the block is one detector
+//           with more rows, read through the CSR lists instead);
+//   words 1 .. 20: the rows (measurement indices), or word 1 = that detector;
+//   words 21 .. 36: the detectors;
+//   words 37 .. 52: per detector, the rows it XORs (bit r = row r; a row named
+//           twice cancels).
+constexpr uint32_t kDetBlockWords = 64, kDetBlockRows = 20, kDetBlockDets = 16;
+constexpr uint32_t kDetBlockCsr = 1u << 31;
 
 struct CompileError {
   int code;          // STIM_E_*

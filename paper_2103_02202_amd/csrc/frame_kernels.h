@@ -115,5 +115,8 @@ uint32_t batch_waves_per_block(uint64_t n, int T);
 // idx[off[r] .. off[r+1]).  Rows are visited in `order` (NULL: 0, 1, ...).
 hipError_t launch_parity(const uint64_t *flips, uint64_t W, const uint32_t *off, const uint32_t *idx,
                          const uint32_t *order, uint32_t rows, uint64_t *out, hipStream_t stream);
+// Detection events by detector blocks (Program::det_blocks, nblocks of them).
+hipError_t launch_parity_blocks(const uint64_t *flips, uint64_t W, const uint32_t *blocks, uint64_t nblocks,
+                                const uint32_t *off, const uint32_t *idx, uint64_t *out, hipStream_t stream);
 
 }  // namespace stimgpu

@@ -1035,6 +1035,49 @@ __global__ void __launch_bounds__(256) k_parity(const uint64_t *__restrict__ fli
   }
 }
 
+// Detection events by blocks of the chained detector order (Sec. 5.6): a
+// workgroup takes one block and VEC adjacent words per thread, issues the
+// loads of all the block's flip rows (at most kDetBlockRows) before using any,
+// then XORs each detector's rows from registers.  The block descriptor is
+// uniform and never written, so it is read with scalar loads.  A block that is
+// one detector with more rows goes through the CSR lists.
+template <int VEC>
+__global__ void __launch_bounds__(256) k_parity_blocks(const uint64_t *__restrict__ flips, uint64_t W,
+                                                       const uint32_t *__restrict__ blocks, uint32_t xb,
+                                                       const uint32_t *__restrict__ off,
+                                                       const uint32_t *__restrict__ idx, uint64_t *__restrict__ out) {
+  typedef uint64_t V2 __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<VEC == 2, V2, uint64_t>::type V;
+  typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+  const uint32_t blk = blockIdx.x / xb, xpart = blockIdx.x % xb;
+  const uint64_t w = ((uint64_t)xpart * blockDim.x + threadIdx.x) * VEC;
+  if (w >= W) return;
+  ConstU32 *dsc = (ConstU32 *)(blocks + (size_t)blk * kDetBlockWords);
+  const uint32_t head = dsc[0];
+  if (head & kDetBlockCsr) {
+    const uint32_t d = dsc[1];
+    V acc = V(0);
+    for (uint32_t k = off[d]; k < off[d + 1]; k++) acc ^= *reinterpret_cast<const V *>(flips + (uint64_t)idx[k] * W + w);
+    *reinterpret_cast<V *>(out + (uint64_t)d * W + w) = acc;
+    return;
+  }
+  const uint32_t ndet = head & 0xFFu, nrows = (head >> 8) & 0xFFu;
+  V row[kDetBlockRows];
+#pragma unroll
+  for (uint32_t r = 0; r < kDetBlockRows; r++)
+    row[r] = r < nrows ? *reinterpret_cast<const V *>(flips + (uint64_t)dsc[1 + r] * W + w) : V(0);
+#pragma unroll
+  for (uint32_t i = 0; i < kDetBlockDets; i++) {
+    if (i >= ndet) break;
+    const uint32_t mask = dsc[1 + kDetBlockRows + kDetBlockDets + i];
+    V acc = V(0);
+#pragma unroll
+    for (uint32_t r = 0; r < kDetBlockRows; r++)
+      if ((mask >> r) & 1u) acc ^= row[r];
+    *reinterpret_cast<V *>(out + (uint64_t)dsc[1 + kDetBlockRows + i] * W + w) = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -1163,6 +1206,23 @@ hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t in
     case 32: hipLaunchKernelGGL(k_noise_gen<32>, grid, block, lds, stream, g); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_parity_blocks(const uint64_t *flips, uint64_t W, const uint32_t *blocks, uint64_t nblocks,
+                                const uint32_t *off, const uint32_t *idx, uint64_t *out, hipStream_t stream) {
+  if (nblocks == 0 || W == 0) return hipSuccess;
+  const uint32_t threads = 256;
+  const int vec = W % 2 == 0 && (uintptr_t)out % 16 == 0 && (uintptr_t)flips % 16 == 0 ? 2 : 1;
+  const uint64_t xb = (W / vec + threads - 1) / threads;
+  if (xb * nblocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)(xb * nblocks));
+  if (vec == 2)
+    hipLaunchKernelGGL(k_parity_blocks<2>, grid, dim3(threads), 0, stream, flips, W, blocks, (uint32_t)xb, off, idx,
+                       out);
+  else
+    hipLaunchKernelGGL(k_parity_blocks<1>, grid, dim3(threads), 0, stream, flips, W, blocks, (uint32_t)xb, off, idx,
+                       out);
   return hipGetLastError();
 }
 
