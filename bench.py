@@ -58,11 +58,11 @@ HBM_PEAK_GBS = 8000.0
 # written.  The counters hold for the library sources whose digest is
 # PMC_SOURCES; once any of them changes, `traffic` is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-PMC_KIB = {"k_frame": (360573.0, 990266.2)}     # FETCH_SIZE KiB, WRITE_SIZE KiB per dispatch
+PMC_KIB = {"k_frame": (360553.9, 991260.9)}     # FETCH_SIZE KiB, WRITE_SIZE KiB per dispatch
 # SQ counters of the same kernel and workload (per dispatch): what bounds it.
 PMC_SQ = {"SQ_INSTS_VALU": 9.018e8, "SQ_BUSY_CU_CYCLES": 1.606e9, "SQ_LDS_IDX_ACTIVE": 4.382e8,
-          "SQ_LDS_BANK_CONFLICT": 1.959e8, "SQ_WAIT_ANY": 2.800e9, "SQ_WAVE_CYCLES": 6.424e9}
-PMC_SOURCES = "6f8b5020244e91df"                  # sources_digest() when the counters were taken
+          "SQ_LDS_BANK_CONFLICT": 1.959e8, "SQ_WAIT_ANY": 2.800e9, "SQ_WAVE_CYCLES": 6.429e9}
+PMC_SOURCES = "ce418a0be6bddc62"                  # sources_digest() when the counters were taken
 PMC_PROFILE = "profiles/k_frame_surface_d49_65536shots.md"
 CUS, CLOCK_HZ = 256, 2.4e9
 
