@@ -118,7 +118,9 @@ int stim_frame_sample(stim_circuit *c, uint64_t seed, uint64_t shot_offset, uint
  * per circuit by the backward walk behind stim_error_sets), the walk skips the
  * Z randomisations after collapses: each would add to the events the detector
  * set of a Z error at that point, which is then empty, so the events are the
- * same bits (STIM_EVENT_ZRAND=1 keeps the draws).  With STIM_WALK_EVENTS=1 the walk forms the events itself from a
+ * same bits (STIM_EVENT_ZRAND=1 keeps the draws); an M followed by an R of
+ * the same qubits then resets them itself (M, R is MR without the draws).
+ * With STIM_WALK_EVENTS=1 the walk forms the events itself from a
  * per-workgroup ring of its recent flips (longest detector, observable or
  * feedback lookback plus the largest measurement instruction, at most the
  * whole record, in rows of the tile's words) when those rings fit in 512 MiB.

@@ -249,6 +249,36 @@ int ensure_noz_program(stim_circuit *c, DeviceCopy *d, hipStream_t s) {
     op.code &= ~OPF_ZRAND_LIVE;
     for (uint32_t k = 0; k < op.n; k++) tg[(size_t)op.toff + k] |= TGT_DEAD_ZRAND;
   }
+  // M followed by an R of the same qubits: the M resets them (see OPF_M_RESETS).
+  auto same_qubits = [&](const DevOp &a, const DevOp &b) {
+    if (a.n != b.n) return false;
+    std::vector<uint32_t> x(tg.begin() + a.toff, tg.begin() + a.toff + a.n);
+    std::vector<uint32_t> y(tg.begin() + b.toff, tg.begin() + b.toff + b.n);
+    std::sort(x.begin(), x.end());
+    std::sort(y.begin(), y.end());
+    return x == y;
+  };
+  auto is_r = [&](size_t pc) { return pc < ops.size() && (ops[pc].code & 0xFFFFu) == OP_R; };
+  for (size_t pc = 0; pc + 1 < ops.size(); pc++) {
+    if ((ops[pc].code & 0xFFFFu) != OP_M) continue;
+    const uint32_t next = ops[pc + 1].code & 0xFFFFu;
+    size_t r = 0;
+    uint32_t flag = 0;
+    if (is_r(pc + 1)) {
+      r = pc + 1;
+      flag = OPF_M_RESETS;
+    } else if (next == OP_LOOP_BEGIN && is_r(pc + 2)) {
+      r = pc + 2;
+      flag = OPF_M_RESETS;
+    } else if (next == OP_LOOP_END && is_r((size_t)ops[pc + 1].aux + 1)) {
+      r = (size_t)ops[pc + 1].aux + 1;
+      flag = OPF_M_RESETS_IN_LOOP;
+    }
+    if (flag && same_qubits(ops[pc], ops[r])) {
+      ops[pc].code |= flag;
+      ops[r].code |= OPF_R_AFTER_M;
+    }
+  }
   hipError_t e;
   DevOp *dops = nullptr;
   uint32_t *dtg = nullptr;

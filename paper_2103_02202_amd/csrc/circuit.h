@@ -81,6 +81,12 @@ constexpr uint32_t TGT_QUBIT_MASK = ~TGT_DEAD_ZRAND;
 constexpr uint32_t TGT_FB_LOCAL = 1u << 31;
 // Flag in OpCode word of a classically controlled op: every pair is local.
 constexpr uint32_t OPF_FB_LOCAL = 1u << 18;
+// Flags of the detector-mode program without Z randomisations: an M whose
+// next frame op is an R of the same qubits resets them itself, right after
+// measuring (always, or only when its enclosing loop goes round again and the
+// R starts the loop body); that R then does nothing when it follows a reset
+// M.  With the randomisations gone, M then R is exactly MR.
+constexpr uint32_t OPF_M_RESETS = 1u << 19, OPF_M_RESETS_IN_LOOP = 1u << 20, OPF_R_AFTER_M = 1u << 21;
 
 // Device program entry (32 bytes).
 struct DevOp {

@@ -781,6 +781,8 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint32_t loop_left[8];
   int depth = 0;
   uint32_t noise_seq = 0;
+  uint32_t inner_left = 0;       // passes left of the innermost loop, this one included
+  bool reset_done = false;       // the last collapse was an M that also did the next R
   // Two-stage prefetch of the next noise execution's records.  Stage A (at a
   // noise op) loads the next execution's {count, first record}: the same for
   // the whole workgroup, and never written by the walk, so a scalar load
@@ -822,12 +824,14 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     if (code == OP_LOOP_BEGIN) {
       flat += op.lead;
       loop_left[depth++] = op.aux;
+      inner_left = op.aux;
       continue;
     }
     if (code == OP_LOOP_END) {
       flat += op.lead;
       if (--loop_left[depth - 1] > 0) pc = op.aux;    // back to the loop begin; body follows
       else depth--;
+      inner_left = depth > 0 ? loop_left[depth - 1] : 0u;
       continue;
     }
     if constexpr (EVENTS) {      // event ops (only in the events program): no flat index, no barrier
@@ -851,7 +855,16 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       instr = flat - 1;
     }
     if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
-      collapse_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, code, instr, meas, ring, ring_pos, stage_b);
+      // An R that a reset M already did (uniform): nothing to do, no barrier.
+      if (code == OP_R && reset_done && (op.code & OPF_R_AFTER_M)) {
+        reset_done = false;
+        continue;
+      }
+      reset_done = false;
+      const bool resets = code == OP_M && ((op.code & OPF_M_RESETS) || ((op.code & OPF_M_RESETS_IN_LOOP) && inner_left > 1));
+      if (resets) reset_done = true;
+      collapse_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, resets ? (uint32_t)OP_MR : code, instr, meas, ring, ring_pos,
+                                           stage_b);
     } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
       const uint32_t inst = noise_seq++;
       uint32_t count = kNoRecords;                 // same value in every thread

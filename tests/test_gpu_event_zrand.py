@@ -117,3 +117,51 @@ def test_batched_requests_use_the_same_program(sg):
             want = oracle.Circuit(t).sample(20 + i, 0, 3000, det=True, obs=True, meas=False)
             assert np.array_equal(r["out0"].cpu().numpy().view(np.uint64), want["det"]), f"request {i}"
             assert np.array_equal(r["out1"][: c.num_observables].cpu().numpy().view(np.uint64), want["obs"])
+
+
+MEASURE_THEN_RESET = """R 0 1 2 3 4
+CX 0 1 2 3
+CX 2 1 4 3
+M 1 3
+DETECTOR rec[-2]
+DETECTOR rec[-1]
+R 3 1
+X_ERROR(0.05) 0 2 4
+CX 0 1 2 3
+CX 2 1 4 3
+M 1 3
+DETECTOR rec[-2] rec[-4]
+DETECTOR rec[-1] rec[-3]
+REPEAT 5 {
+    R 1 3
+    DEPOLARIZE1(0.02) 0 2 4
+    CX 0 1 2 3
+    CX 2 1 4 3
+    X_ERROR(0.03) 1 3
+    M 1 3
+    DETECTOR rec[-2] rec[-4]
+    DETECTOR rec[-1] rec[-3]
+}
+M 1
+DETECTOR rec[-1] rec[-3]
+R 1 3
+CX 0 1 2 3
+M 1 3
+DETECTOR rec[-2]
+DETECTOR rec[-1]
+M 0 2 4
+OBSERVABLE_INCLUDE(0) rec[-1]
+"""
+
+
+def test_measure_then_reset_done_as_one_op(sg, monkeypatch):
+    """Without the draws, an M followed by an R of the same qubits (directly,
+    in another order; across the start of a loop; across its back edge) resets
+    them itself and the R is skipped; an R of other qubits is not.  Events
+    equal the oracle's and those of the program that keeps every op."""
+    announce("measure then reset")
+    (da, oa), (db, ob) = both_ways(sg, MEASURE_THEN_RESET, 13, 5000, monkeypatch)
+    want = oracle.Circuit(MEASURE_THEN_RESET).sample(13, 0, 5000, det=True, obs=True, meas=False)
+    assert np.array_equal(da, want["det"]) and np.array_equal(oa, want["obs"])
+    assert np.array_equal(db, want["det"]) and np.array_equal(ob, want["obs"])
+    assert np.count_nonzero(da) > 0
