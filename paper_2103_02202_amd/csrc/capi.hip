@@ -762,7 +762,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.word0 = p.word0;
     g.num_words = W;
     g.tiles = (uint32_t)ntiles;
-    g.meta_stride = (uint32_t)ntiles;
+    g.meta_stride = (uint32_t)ninst;          // meta is [tile][execution]
     g.meta = d_meta;
     g.rec = d_rec;
     // Each workgroup takes as many tiles of one execution as its LDS queue
@@ -1083,7 +1083,7 @@ hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
     g.word0 = r.shot_offset / 64;
     g.num_words = W;
     g.tiles = (uint32_t)((W + T - 1) / T);
-    g.meta_stride = nz.stride;
+    g.meta_stride = (uint32_t)nz.ninst;       // meta is [tile][execution]
     g.meta = nz.meta;
     g.rec = nz.rec;
     g.tiles_per_group = std::max<uint32_t>(1, std::min<uint32_t>(kGenTiles, kGenQueue / nz.max_cap[k]));

@@ -24,7 +24,7 @@ struct FrameParams {
   uint64_t out_stride;
   uint64_t *scratch;            // global frame slices when not in LDS
   // Precomputed noise (k_noise_gen), or noise_meta == NULL to draw it inline.
-  // noise_meta[execution][tile] = {record count (kNoRecords: draw inline),
+  // noise_meta[tile][execution] = {record count (kNoRecords: draw inline),
   // index of the first record in noise_rec}.
   const uint2 *noise_meta;
   const uint4 *noise_rec;       // 16-byte records
@@ -59,10 +59,10 @@ struct NoiseGenParams {
   const uint32_t *cap;          // [instances] 0: leave to the walker
   uint64_t seed, word0, num_words;
   uint32_t tiles;
-  uint32_t meta_stride;         // meta entries per instance (>= tiles)
+  uint32_t meta_stride;         // meta entries per tile (>= instances)
   uint32_t tiles_per_group;     // tiles per workgroup (at most kGenTiles)
   uint32_t queue_per_tile;      // LDS queue entries per tile (tiles_per_group * this <= kGenQueue)
-  uint2 *meta;                  // [instances][meta_stride] {count, first record}
+  uint2 *meta;                  // [tiles][meta_stride] {count, first record}
   uint4 *rec;
 };
 

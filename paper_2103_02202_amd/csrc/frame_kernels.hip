@@ -606,11 +606,11 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   const uint32_t inst = blockIdx.y;
   const uint32_t t0 = blockIdx.x * g.tiles_per_group;
   const uint32_t S = g.tiles - t0 < g.tiles_per_group ? g.tiles - t0 : g.tiles_per_group;
-  uint2 *meta = g.meta + (size_t)inst * g.meta_stride + t0;
+  uint2 *meta = g.meta + (size_t)t0 * g.meta_stride + inst;     // [tile][execution]: entry t at meta[t * stride]
   const uint32_t cap = g.cap[inst];
   const uint64_t base = g.base[inst];
   if (cap == 0) {
-    if (threadIdx.x < S) meta[threadIdx.x] = make_uint2(kNoRecords, 0u);
+    if (threadIdx.x < S) meta[(size_t)threadIdx.x * g.meta_stride] = make_uint2(kNoRecords, 0u);
     return;
   }
   const DevOp op = g.ops[g.inst_pc[inst]];
@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   if (threadIdx.x < S) {
     const uint32_t t = threadIdx.x;
     const bool ok = s_cnt[t] <= qcap && !s_bad[t];
-    meta[t] = make_uint2(ok ? s_cnt[t] : kNoRecords, (uint32_t)(base + (uint64_t)(t0 + t) * cap));
+    meta[(size_t)t * g.meta_stride] = make_uint2(ok ? s_cnt[t] : kNoRecords, (uint32_t)(base + (uint64_t)(t0 + t) * cap));
   }
 }
 
@@ -796,7 +796,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint2 a_meta = make_uint2(kNoRecords, 0u);
   auto stage_a = [&](uint32_t inst) {
     const bool ok = recs && inst < p.noise_instances;
-    const uint32_t *src = ok ? (const uint32_t *)(p.noise_meta + (size_t)inst * p.noise_tiles + tile) : kNoMeta;
+    const uint32_t *src = ok ? (const uint32_t *)(p.noise_meta + (size_t)tile * p.noise_instances + inst) : kNoMeta;
     a_meta = load_meta(src);
     a_inst = ok ? inst : 0xFFFFFFFFu;
   };
@@ -1204,7 +1204,7 @@ hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t in
                             hipStream_t stream) {
   if (instances == 0 || g.tiles == 0) return hipSuccess;
   if (instances > 65535 || threads == 0 || threads % 64 || threads > 512 || g.tiles_per_group == 0 ||
-      g.meta_stride < g.tiles ||
+      g.meta_stride < instances ||                 // meta is [tiles][meta_stride]
       g.tiles_per_group > kGenTiles || g.queue_per_tile == 0 ||
       (size_t)g.tiles_per_group * g.queue_per_tile > kGenQueue)
     return hipErrorInvalidValue;
