@@ -32,10 +32,11 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
 
 // One workgroup (1024 threads) per block of kTransposeChunks x 64 rows x 16
 // words: coalesced 128-byte row segments into LDS, then each wave transposes
-// the kTransposeChunks 64 x 64 blocks of one word column and writes each of
-// its 64 shots' chunks as one contiguous piece of 8 kTransposeChunks bytes
-// (T rows are padded to a multiple of kTransposeChunks chunks), so that a
-// shot's piece covers whole 64-byte lines.
+// the kTransposeChunks 64 x 64 blocks of one word column; each of the 1024
+// shots' chunks form one contiguous piece of 8 kTransposeChunks bytes (T rows
+// are padded to a multiple of kTransposeChunks chunks), staged in LDS and
+// written by four consecutive lanes, so that a shot's piece covers whole
+// 64-byte lines and a store instruction 16 of them.
 // B8: instead of T, write the b8 bytes directly -- bytes [64 cg, 64 cg + 64)
 // of shot s's row, clipped to its nbytes, at out + s nbytes (nbytes a
 // multiple of 4, so every piece starts on a 4-byte boundary; other widths go
@@ -73,27 +74,43 @@ __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__
   uint64_t y[NB];
 #pragma unroll
   for (uint32_t h = 0; h < NB; h++) y[h] = bit_transpose64(tile[h * 64 + lane][k], lane);
-  const uint64_t s = (w0 + k) * 64 + lane;
-  if (s < shots) {
+  // Stage each shot's 8 NB bytes shot-major in LDS (the input tile is no
+  // longer needed; word h of local shot ls sits at ls NB + (h ^ (ls & 7)), a
+  // swizzle that spreads a wave's writes over the banks), then write them
+  // with four consecutive lanes per shot: a store instruction covers 16
+  // whole 64-byte pieces instead of 64 scattered 16-byte ones.
+  static_assert(NB == 8, "staging assumes 64-byte pieces");
+  __syncthreads();
+  uint64_t *stage = tile_mem;                                       // [1024 local shots][NB]
+  {
+    const uint32_t ls = k * 64 + lane;
+#pragma unroll
+    for (uint32_t h = 0; h < NB; h++) stage[ls * NB + (h ^ (ls & 7))] = y[h];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t i = 0; i < 4; i++) {
+    const uint32_t q = threadIdx.x + i * 1024, ls = q >> 2, part = q & 3;
+    const uint64_t s = w0 * 64 + ls;
+    if (s >= shots) continue;
+    const uint64_t a = stage[ls * NB + ((2 * part) ^ (ls & 7))];
+    const uint64_t b = stage[ls * NB + ((2 * part + 1) ^ (ls & 7))];
     if constexpr (B8) {
       typedef uint32_t U32x4a __attribute__((ext_vector_type(4), aligned(4)));
-      const uint64_t b0 = (uint64_t)cg * NB * 8;                 // < nbytes: group cg holds row bits
-      uint8_t *row = out + s * nbytes + b0;
-      if (nbytes - b0 >= NB * 8) {
-#pragma unroll
-        for (uint32_t h = 0; h < NB; h += 2)
-          reinterpret_cast<U32x4a *>(row)[h / 2] = U32x4a{(uint32_t)y[h], (uint32_t)(y[h] >> 32),
-                                                          (uint32_t)y[h + 1], (uint32_t)(y[h + 1] >> 32)};
+      const uint64_t off = (uint64_t)cg * NB * 8 + 16 * part;      // byte offset of the piece in row s
+      if (off >= nbytes) continue;
+      uint8_t *piece = out + s * nbytes + off;
+      if (nbytes - off >= 16) {
+        *reinterpret_cast<U32x4a *>(piece) = U32x4a{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
       } else {
-        const uint32_t nw = (uint32_t)(nbytes - b0) / 4;
+        const uint32_t nw = (uint32_t)(nbytes - off) / 4;       // nbytes is a multiple of 4
+        const uint32_t w[4] = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
 #pragma unroll
-        for (uint32_t i = 0; i < 2 * NB; i++)
-          if (i < nw) reinterpret_cast<uint32_t *>(row)[i] = (uint32_t)(y[i / 2] >> (32 * (i & 1)));
+        for (uint32_t t = 0; t < 3; t++)
+          if (t < nw) reinterpret_cast<uint32_t *>(piece)[t] = w[t];
       }
     } else {
-      V2 *dst = reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * NB);
-#pragma unroll
-      for (uint32_t h = 0; h < NB; h += 2) dst[h / 2] = V2{y[h], y[h + 1]};
+      *reinterpret_cast<V2 *>(T + s * tstride + (uint64_t)cg * NB + 2 * part) = V2{a, b};
     }
   }
 }
