@@ -117,31 +117,41 @@ __global__ void __launch_bounds__(1024) k_transpose(const uint64_t *__restrict__
 
 // b8: shot s's bytes are the first nbytes bytes of T[s] (T rows are
 // little-endian bit strings), packed back to back.  A thread writes one
-// aligned 4-byte word of the output that lies inside row s, assembled from
-// two aligned words of T; the at most three bytes at either end of a row that
-// share an output word with the neighbouring row are written singly.
+// aligned 16-byte piece of the output that lies inside row s, funnel-shifted
+// out of five aligned 4-byte words of T (every word it reads starts inside
+// the row's bytes, and T rows are padded to whole 64-byte chunks); the at
+// most fifteen bytes at either end of a row that share a piece with the
+// neighbouring row are written singly.
 __global__ void __launch_bounds__(256) k_b8(const uint64_t *__restrict__ T, uint32_t tstride, uint64_t shots,
                                             uint64_t nbytes, uint8_t *__restrict__ out) {
+  typedef uint32_t U32x4 __attribute__((ext_vector_type(4), aligned(4)));   // `out` is 4-byte aligned
   const uint32_t *src32 = reinterpret_cast<const uint32_t *>(T);
   const uint8_t *src8 = reinterpret_cast<const uint8_t *>(T);
-  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // output word within the row's span
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // output piece within the row's span
   for (uint64_t s = blockIdx.y; s < shots; s += gridDim.y) {
     const uint64_t a0 = s * nbytes, a1 = a0 + nbytes;                    // row s occupies [a0, a1)
-    const uint64_t first = (a0 + 3) / 4, last = a1 / 4;                  // whole output words [first, last)
+    const uint64_t first = (a0 + 15) / 16, last = a1 / 16;              // whole output pieces [first, last)
     const uint64_t tw = (uint64_t)s * tstride * 2;                       // row s in 32-bit words of T
-    const uint64_t ow = first + q;
-    if (ow < last) {
-      const uint64_t b = ow * 4 - a0;                                    // byte offset inside row s
+    const uint64_t op = first + q;
+    if (op < last) {
+      const uint64_t b = op * 16 - a0;                                   // byte offset inside row s
       const uint32_t sh = (uint32_t)(b & 3) * 8;
-      const uint32_t lo = src32[tw + (b >> 2)];
-      const uint32_t hi = sh ? src32[tw + (b >> 2) + 1] : 0u;
-      const uint32_t v = sh ? (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) : lo;
-      reinterpret_cast<uint32_t *>(out)[ow] = v;
+      const uint32_t *w = src32 + tw + (b >> 2);
+      const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+      U32x4 v;
+      if (sh) {
+        const uint32_t w4 = w[4];
+        v = U32x4{(uint32_t)((((uint64_t)w1 << 32) | w0) >> sh), (uint32_t)((((uint64_t)w2 << 32) | w1) >> sh),
+                  (uint32_t)((((uint64_t)w3 << 32) | w2) >> sh), (uint32_t)((((uint64_t)w4 << 32) | w3) >> sh)};
+      } else {
+        v = U32x4{w0, w1, w2, w3};
+      }
+      reinterpret_cast<U32x4 *>(out)[op] = v;
     }
-    if (q < 4) {                                                         // ragged ends of the row
-      const uint64_t head = first * 4 - a0 < nbytes ? first * 4 - a0 : nbytes;
+    if (q < 16) {                                                        // ragged ends of the row
+      const uint64_t head = first * 16 - a0 < nbytes ? first * 16 - a0 : nbytes;
       if (q < head) out[a0 + q] = src8[s * tstride * 8 + q];
-      const uint64_t tail_start = last * 4 > a0 + head ? last * 4 : a0 + head;
+      const uint64_t tail_start = last * 16 > a0 + head ? last * 16 : a0 + head;
       if (tail_start + q < a1) out[tail_start + q] = src8[s * tstride * 8 + (tail_start + q - a0)];
     }
   }
@@ -438,8 +448,8 @@ hipError_t launch_transpose_b8(const uint64_t *table, uint64_t rows, uint64_t W,
 hipError_t launch_dense_format(const uint64_t *T, uint64_t rows, uint64_t shots, int b8, uint8_t *out,
                                hipStream_t stream) {
   const uint64_t width = b8 ? (rows + 7) / 8 : rows + 1;
-  // b8: a thread per 4-byte piece; 01: a wave per 512 16-byte pieces.
-  const uint64_t xb = b8 ? (width / 4 + 1 + 255) / 256 : (((width / 16 + 1) + 511) / 512 * 64 + 255) / 256;
+  // b8: a thread per 16-byte piece; 01: a wave per 512 16-byte pieces.
+  const uint64_t xb = b8 ? (width / 16 + 1 + 255) / 256 : (((width / 16 + 1) + 511) / 512 * 64 + 255) / 256;
   if (shots == 0) return hipSuccess;
   if (xb > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const uint32_t tstride = (uint32_t)transpose_stride(rows);

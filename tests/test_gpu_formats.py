@@ -51,7 +51,7 @@ def check(sg, words, rows, shots, fmt):
 @pytest.mark.parametrize("fmt", ["01", "b8", "hits", "r8"])
 @pytest.mark.parametrize("rows,shots,density", [(0, 5, 0.0), (1, 1, 0.5), (7, 70, 0.5), (64, 64, 0.3), (65, 200, 0.1),
                                                 (130, 1000, 0.02), (300, 777, 0.001), (600, 129, 0.0),
-                                                (1000, 300, 1.0), (70, 3000, 0.05),
+                                                (1000, 300, 1.0), (70, 3000, 0.05), (4001, 333, 0.3),
                                                 # b8 rows of a multiple of 4 bytes (written by the transpose)
                                                 (32, 999, 0.2), (224, 64, 0.5), (256, 130, 0.1),
                                                 (800, 257, 0.05), (2080, 1100, 0.01)])
