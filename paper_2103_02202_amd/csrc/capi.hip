@@ -221,6 +221,70 @@ int ensure_error_model(stim_circuit *c) {
   return c->em_code ? set_error(c->em_code, c->em_msg) : STIM_OK;
 }
 
+// In the program without Z randomisations a reset leaves x = z = 0, and a
+// Clifford maps a zero frame to zero, so a Clifford op all of whose qubits
+// are zero for every shot changes nothing (for example H right after the
+// reset of an ancilla): flags it OPF_ZERO_SKIP.  A forward pass over the
+// program tracks which qubits are zero at each op: resets (R, MR, INIT)
+// zero their targets, noise ops and classically controlled ops make theirs
+// nonzero, M keeps the frame, and a Clifford's qubits stay zero only when
+// all the qubits it couples are.  A loop body is analysed from the meet
+// (qubit zero on every entry) of the state before the loop and at the end of
+// the body, until the state at the body's start stops changing.
+static void zero_pass(std::vector<DevOp> &ops, const std::vector<uint32_t> &tg, size_t lo, size_t hi,
+                      std::vector<uint8_t> &zero, bool mark) {
+  for (size_t pc = lo; pc < hi; pc++) {
+    DevOp &op = ops[pc];
+    const uint32_t code = op.code & 0xFFFFu;
+    const uint32_t *t = tg.data() + op.toff;
+    if (code == OP_LOOP_BEGIN) {
+      const size_t end = op.aux2;                  // pc of the matching loop end
+      std::vector<uint8_t> in = zero;
+      for (int it = 0; it < 64; it++) {
+        std::vector<uint8_t> st = in;
+        zero_pass(ops, tg, pc + 1, end, st, false);
+        bool changed = false;
+        for (size_t q = 0; q < in.size(); q++) {
+          const uint8_t m = in[q] & st[q];
+          changed |= m != in[q];
+          in[q] = m;
+        }
+        if (!changed) break;
+      }
+      zero = in;
+      zero_pass(ops, tg, pc + 1, end, zero, mark);  // the state after the loop: the last pass's end
+      pc = end;
+      continue;
+    }
+    if (code == OP_INIT || code == OP_R || code == OP_MR) {
+      for (uint32_t k = 0; k < op.n; k++) zero[t[k] & TGT_QUBIT_MASK] = 1;
+    } else if (code == OP_M) {
+      // M keeps the frame; one that always resets zeroes it (one that resets
+      // only when its loop goes round again leaves zero qubits zero).
+      if (op.code & OPF_M_RESETS)
+        for (uint32_t k = 0; k < op.n; k++) zero[t[k] & TGT_QUBIT_MASK] = 1;
+    } else if (code >= OP_SWAP_XZ && code <= OP_SWAP) {
+      const bool two = code >= OP_CX;
+      bool all = true;
+      for (uint32_t k = 0; k < op.n * (two ? 2u : 1u); k++) all &= zero[t[k]] != 0;
+      if (two)
+        for (uint32_t k = 0; k < op.n; k++) {
+          const bool z = zero[t[2 * k]] && zero[t[2 * k + 1]];
+          zero[t[2 * k]] = zero[t[2 * k + 1]] = z;
+        }
+      if (mark && all) op.code |= OPF_ZERO_SKIP;
+    } else if ((code >= OP_NOISE_X && code <= OP_NOISE_DEP2) || (code >= OP_FB_X && code <= OP_FB_Z)) {
+      const uint32_t per = code == OP_NOISE_DEP2 ? 2u : 1u, stride = code >= OP_FB_X ? 2u : 1u;
+      for (uint32_t k = 0; k < op.n * per; k++) zero[t[k * stride] & TGT_QUBIT_MASK] = 0;
+    }
+  }
+}
+
+static void mark_zero_frame_ops(std::vector<DevOp> &ops, const std::vector<uint32_t> &tg, uint64_t n) {
+  std::vector<uint8_t> zero(n, 0);
+  zero_pass(ops, tg, 0, ops.size(), zero, true);
+}
+
 // Detection events without the collapses' Z randomisations (Sec. 3, 5.6).
 // The frame is linear over GF(2) in its random bits, so the Z randomisation
 // drawn after a collapse adds to the events exactly the detector set of a Z
@@ -279,6 +343,7 @@ int ensure_noz_program(stim_circuit *c, DeviceCopy *d, hipStream_t s) {
       ops[r].code |= OPF_R_AFTER_M;
     }
   }
+  mark_zero_frame_ops(ops, tg, P.num_qubits);
   hipError_t e;
   DevOp *dops = nullptr;
   uint32_t *dtg = nullptr;

@@ -87,6 +87,9 @@ constexpr uint32_t OPF_FB_LOCAL = 1u << 18;
 // R starts the loop body); that R then does nothing when it follows a reset
 // M.  With the randomisations gone, M then R is exactly MR.
 constexpr uint32_t OPF_M_RESETS = 1u << 19, OPF_M_RESETS_IN_LOOP = 1u << 20, OPF_R_AFTER_M = 1u << 21;
+// Flag of the same program on a Clifford op whose qubits are all zero in
+// every shot's frame when it runs (a Clifford maps zero to zero): skipped.
+constexpr uint32_t OPF_ZERO_SKIP = 1u << 22;
 
 // Device program entry (32 bytes).
 struct DevOp {

@@ -894,6 +894,7 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     } else if (code >= OP_FB_X) {
       feedback_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, code, meas, ring, ring_pos);
     } else {
+      if (op.code & OPF_ZERO_SKIP) continue;      // its qubits are zero in every shot: nothing changes
       switch (code) {
         case OP_SWAP_XZ: clifford_op<T, IN_LDS, WAVE, OP_SWAP_XZ>(p, tl, op, stage_b); break;
         case OP_Z_XOR_X: clifford_op<T, IN_LDS, WAVE, OP_Z_XOR_X>(p, tl, op, stage_b); break;
