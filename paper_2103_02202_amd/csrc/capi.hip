@@ -738,6 +738,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
   // noz: the detector-mode program without Z randomisations (same op list).
   const bool use_noz = noz && d->noz_ops != nullptr;
   p.ops = use_noz ? d->noz_ops : d->ops;
+  p.noz = use_noz && ev == nullptr;          // also picks the records table layout below
   p.num_ops = (uint32_t)c->prog.ops.size();
   p.num_qubits = (uint32_t)c->prog.num_qubits;
   p.targets = use_noz ? d->noz_targets : d->targets;
@@ -827,7 +828,10 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     g.word0 = p.word0;
     g.num_words = W;
     g.tiles = (uint32_t)ntiles;
-    g.meta_stride = (uint32_t)ninst;          // meta is [tile][execution]
+    // Tile-major records table for the walk of the program without Z
+    // randomisations, execution-major for the others.
+    g.tile_stride = p.noz ? (uint32_t)ninst : 1u;
+    g.inst_stride = p.noz ? 1u : (uint32_t)ntiles;
     g.meta = d_meta;
     g.rec = d_rec;
     // Each workgroup takes as many tiles of one execution as its LDS queue
@@ -876,6 +880,7 @@ int run_frame(stim_circuit *c, DeviceCopy *d, uint64_t seed, uint64_t shot_offse
     }
     cfg.slots = (uint32_t)slots;
     p.ops = d->event_ops;
+    p.noz = false;
     p.num_ops = (uint32_t)P.event_ops.size();
     p.ring_rows = ring_rows(P);
     p.det_out = ev->det_out;
@@ -1148,7 +1153,8 @@ hipError_t enqueue_plan(BatchPlan &pl, hipStream_t s) {
     g.word0 = r.shot_offset / 64;
     g.num_words = W;
     g.tiles = (uint32_t)((W + T - 1) / T);
-    g.meta_stride = (uint32_t)nz.ninst;       // meta is [tile][execution]
+    g.tile_stride = (uint32_t)nz.ninst;       // batched walks read the table tile-major
+    g.inst_stride = 1u;
     g.meta = nz.meta;
     g.rec = nz.rec;
     g.tiles_per_group = std::max<uint32_t>(1, std::min<uint32_t>(kGenTiles, kGenQueue / nz.max_cap[k]));
@@ -1613,6 +1619,7 @@ int stim_detector_sample_noalloc(stim_circuit *c, uint64_t seed, uint64_t shot_o
   uint64_t *flips = (uint64_t *)base;
   FrameParams p{};
   p.ops = ops;
+  p.noz = ops != nullptr && d != nullptr && ops == d->noz_ops;
   p.num_ops = (uint32_t)P.ops.size();
   p.num_qubits = (uint32_t)P.num_qubits;
   p.targets = targets;

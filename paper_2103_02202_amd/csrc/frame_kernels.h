@@ -24,7 +24,9 @@ struct FrameParams {
   uint64_t out_stride;
   uint64_t *scratch;            // global frame slices when not in LDS
   // Precomputed noise (k_noise_gen), or noise_meta == NULL to draw it inline.
-  // noise_meta[tile][execution] = {record count (kNoRecords: draw inline),
+  // noise_meta[tile][execution] (walks with noz set, and batched walks) or
+  // noise_meta[execution][noise_tiles] (otherwise) = {record count
+  // (kNoRecords: draw inline),
   // index of the first record in noise_rec}.
   const uint2 *noise_meta;
   const uint4 *noise_rec;       // 16-byte records
@@ -40,6 +42,9 @@ struct FrameParams {
   uint64_t *obs_out;
   uint32_t ring_rows;
   uint32_t num_obs;
+  // The program is the one without Z randomisations (its walk honours the
+  // flags that program carries).
+  bool noz;
 };
 
 // Record count meaning "draw this noise op inline".
@@ -59,10 +64,14 @@ struct NoiseGenParams {
   const uint32_t *cap;          // [instances] 0: leave to the walker
   uint64_t seed, word0, num_words;
   uint32_t tiles;
-  uint32_t meta_stride;         // meta entries per tile (>= instances)
+  // Entry (tile t, execution e) at meta[t * tile_stride + e * inst_stride]:
+  // tile-major (inst_stride 1, tile_stride >= instances) for walks of the
+  // program without Z randomisations, else execution-major (tile_stride 1,
+  // inst_stride >= tiles); see FrameParams::noise_meta.
+  uint32_t tile_stride, inst_stride;
   uint32_t tiles_per_group;     // tiles per workgroup (at most kGenTiles)
   uint32_t queue_per_tile;      // LDS queue entries per tile (tiles_per_group * this <= kGenQueue)
-  uint2 *meta;                  // [tiles][meta_stride] {count, first record}
+  uint2 *meta;                  // {count, first record}
   uint4 *rec;
 };
 

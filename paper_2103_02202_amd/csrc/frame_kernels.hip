@@ -606,11 +606,11 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   const uint32_t inst = blockIdx.y;
   const uint32_t t0 = blockIdx.x * g.tiles_per_group;
   const uint32_t S = g.tiles - t0 < g.tiles_per_group ? g.tiles - t0 : g.tiles_per_group;
-  uint2 *meta = g.meta + (size_t)t0 * g.meta_stride + inst;     // [tile][execution]: entry t at meta[t * stride]
+  uint2 *meta = g.meta + (size_t)t0 * g.tile_stride + (size_t)inst * g.inst_stride;   // entry t at meta[t * tile_stride]
   const uint32_t cap = g.cap[inst];
   const uint64_t base = g.base[inst];
   if (cap == 0) {
-    if (threadIdx.x < S) meta[(size_t)threadIdx.x * g.meta_stride] = make_uint2(kNoRecords, 0u);
+    if (threadIdx.x < S) meta[(size_t)threadIdx.x * g.tile_stride] = make_uint2(kNoRecords, 0u);
     return;
   }
   const DevOp op = g.ops[g.inst_pc[inst]];
@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(512) k_noise_gen(NoiseGenParams g) {
   if (threadIdx.x < S) {
     const uint32_t t = threadIdx.x;
     const bool ok = s_cnt[t] <= qcap && !s_bad[t];
-    meta[(size_t)t * g.meta_stride] = make_uint2(ok ? s_cnt[t] : kNoRecords, (uint32_t)(base + (uint64_t)(t0 + t) * cap));
+    meta[(size_t)t * g.tile_stride] = make_uint2(ok ? s_cnt[t] : kNoRecords, (uint32_t)(base + (uint64_t)(t0 + t) * cap));
   }
 }
 
@@ -746,7 +746,10 @@ __device__ __forceinline__ uint2 load_meta(const uint32_t *w) {
 
 // Walks the whole program over one tile.  `lds` is the workgroup's dynamic
 // LDS: per-wave queues, one threshold row, then (IN_LDS) the frame slice.
-template <int T, bool IN_LDS, bool WAVE = false, bool EVENTS = false>
+// NOZ: the walk may run the program without Z randomisations, whose flags
+// (an M that resets, an R it makes redundant, Cliffords on zero qubits) it
+// then honours; the measurement-mode walk leaves that state out.
+template <int T, bool IN_LDS, bool WAVE = false, bool EVENTS = false, bool NOZ = true>
 __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, uint32_t slot, uint64_t *lds) {
   const uint32_t nwaves = WAVE ? 1u : blockDim.x >> 6;
   const uint32_t n = p.num_qubits;
@@ -796,7 +799,11 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
   uint2 a_meta = make_uint2(kNoRecords, 0u);
   auto stage_a = [&](uint32_t inst) {
     const bool ok = recs && inst < p.noise_instances;
-    const uint32_t *src = ok ? (const uint32_t *)(p.noise_meta + (size_t)tile * p.noise_instances + inst) : kNoMeta;
+    // Tile-major table for walks of the program without Z randomisations
+    // (consecutive executions share scalar-cache lines), execution-major
+    // otherwise: each layout measured faster for its walk.
+    const size_t at = NOZ ? (size_t)tile * p.noise_instances + inst : (size_t)inst * p.noise_tiles + tile;
+    const uint32_t *src = ok ? (const uint32_t *)(p.noise_meta + at) : kNoMeta;
     a_meta = load_meta(src);
     a_inst = ok ? inst : 0xFFFFFFFFu;
   };
@@ -824,14 +831,14 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     if (code == OP_LOOP_BEGIN) {
       flat += op.lead;
       loop_left[depth++] = op.aux;
-      inner_left = op.aux;
+      if constexpr (NOZ) inner_left = op.aux;
       continue;
     }
     if (code == OP_LOOP_END) {
       flat += op.lead;
       if (--loop_left[depth - 1] > 0) pc = op.aux;    // back to the loop begin; body follows
       else depth--;
-      inner_left = depth > 0 ? loop_left[depth - 1] : 0u;
+      if constexpr (NOZ) inner_left = depth > 0 ? loop_left[depth - 1] : 0u;
       continue;
     }
     if constexpr (EVENTS) {      // event ops (only in the events program): no flat index, no barrier
@@ -855,16 +862,22 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
       instr = flat - 1;
     }
     if (code == OP_INIT || code == OP_R || code == OP_M || code == OP_MR) {
-      // An R that a reset M already did (uniform): nothing to do, no barrier.
-      if (code == OP_R && reset_done && (op.code & OPF_R_AFTER_M)) {
+      uint32_t eff = code;
+      if constexpr (NOZ) {
+        // An R that a reset M already did (uniform): nothing to do, no barrier.
+        if (code == OP_R && reset_done && (op.code & OPF_R_AFTER_M)) {
+          reset_done = false;
+          continue;
+        }
         reset_done = false;
-        continue;
+        const bool resets =
+            code == OP_M && ((op.code & OPF_M_RESETS) || ((op.code & OPF_M_RESETS_IN_LOOP) && inner_left > 1));
+        if (resets) {
+          reset_done = true;
+          eff = OP_MR;
+        }
       }
-      reset_done = false;
-      const bool resets = code == OP_M && ((op.code & OPF_M_RESETS) || ((op.code & OPF_M_RESETS_IN_LOOP) && inner_left > 1));
-      if (resets) reset_done = true;
-      collapse_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, resets ? (uint32_t)OP_MR : code, instr, meas, ring, ring_pos,
-                                           stage_b);
+      collapse_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, eff, instr, meas, ring, ring_pos, stage_b);
     } else if (code >= OP_NOISE_X && code <= OP_NOISE_DEP2) {
       const uint32_t inst = noise_seq++;
       uint32_t count = kNoRecords;                 // same value in every thread
@@ -894,7 +907,8 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
     } else if (code >= OP_FB_X) {
       feedback_op<T, IN_LDS, WAVE, EVENTS>(p, tl, op, code, meas, ring, ring_pos);
     } else {
-      if (op.code & OPF_ZERO_SKIP) continue;      // its qubits are zero in every shot: nothing changes
+      if constexpr (NOZ)
+        if (op.code & OPF_ZERO_SKIP) continue;    // its qubits are zero in every shot: nothing changes
       switch (code) {
         case OP_SWAP_XZ: clifford_op<T, IN_LDS, WAVE, OP_SWAP_XZ>(p, tl, op, stage_b); break;
         case OP_Z_XOR_X: clifford_op<T, IN_LDS, WAVE, OP_Z_XOR_X>(p, tl, op, stage_b); break;
@@ -920,12 +934,13 @@ __device__ __forceinline__ void walk_tile(const FrameParams &p, uint32_t tile, u
 // One workgroup per tile, or (a global frame) a smaller grid of workgroups
 // that take tiles in turn, each reusing its own scratch slot, so that the
 // frames in flight stay within the caches.
-template <int T, bool IN_LDS, bool EVENTS>
+template <int T, bool IN_LDS, bool EVENTS, bool NOZ>
 __global__ void __launch_bounds__(1024) k_frame(FrameParams p) {
   extern __shared__ uint64_t lds[];
   const uint32_t ntiles = (uint32_t)((p.num_words + T - 1) / T);
   const uint32_t first = xcd_tile(blockIdx.x, gridDim.x);
-  for (uint32_t t = first; t < ntiles; t += gridDim.x) walk_tile<T, IN_LDS, false, EVENTS>(p, t, blockIdx.x, lds);
+  for (uint32_t t = first; t < ntiles; t += gridDim.x)
+    walk_tile<T, IN_LDS, false, EVENTS, NOZ>(p, t, blockIdx.x, lds);
 }
 
 // Persistent multi-circuit kernel: every workgroup pops (request, tile) items
@@ -1103,14 +1118,19 @@ template <int T, bool IN_LDS>
 static hipError_t launch_frame_t(const FrameParams &p, uint32_t tiles, uint32_t threads, size_t lds_bytes,
                                  hipStream_t stream) {
   // One instantiation per mode, so that the measurement-mode walk carries
-  // none of the ring's state.
-  const void *k = p.ring ? (const void *)k_frame<T, IN_LDS, true> : (const void *)k_frame<T, IN_LDS, false>;
+  // none of the ring's state, nor that of the program without Z
+  // randomisations.
+  const void *k = p.ring  ? (const void *)k_frame<T, IN_LDS, true, false>
+                  : p.noz ? (const void *)k_frame<T, IN_LDS, false, true>
+                          : (const void *)k_frame<T, IN_LDS, false, false>;
   hipError_t e = allow_dynamic_lds(k, (int)kMaxLdsBytes);
   if (e != hipSuccess) return e;
   if (p.ring)
-    hipLaunchKernelGGL((k_frame<T, IN_LDS, true>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
+    hipLaunchKernelGGL((k_frame<T, IN_LDS, true, false>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
+  else if (p.noz)
+    hipLaunchKernelGGL((k_frame<T, IN_LDS, false, true>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
   else
-    hipLaunchKernelGGL((k_frame<T, IN_LDS, false>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
+    hipLaunchKernelGGL((k_frame<T, IN_LDS, false, false>), dim3(tiles), dim3(threads), lds_bytes, stream, p);
   return hipGetLastError();
 }
 
@@ -1205,7 +1225,7 @@ hipError_t launch_noise_gen(const NoiseGenParams &g, int tile_words, uint32_t in
                             hipStream_t stream) {
   if (instances == 0 || g.tiles == 0) return hipSuccess;
   if (instances > 65535 || threads == 0 || threads % 64 || threads > 512 || g.tiles_per_group == 0 ||
-      g.meta_stride < instances ||                 // meta is [tiles][meta_stride]
+      !((g.inst_stride == 1 && g.tile_stride >= instances) || (g.tile_stride == 1 && g.inst_stride >= g.tiles)) ||
       g.tiles_per_group > kGenTiles || g.queue_per_tile == 0 ||
       (size_t)g.tiles_per_group * g.queue_per_tile > kGenQueue)
     return hipErrorInvalidValue;
