@@ -165,3 +165,47 @@ def test_measure_then_reset_done_as_one_op(sg, monkeypatch):
     assert np.array_equal(da, want["det"]) and np.array_equal(oa, want["obs"])
     assert np.array_equal(db, want["det"]) and np.array_equal(ob, want["obs"])
     assert np.count_nonzero(da) > 0
+
+
+ZERO_ENTRY_ERROR = """R 0 1 2
+X_ERROR(0.3) 0
+REPEAT 4 {
+    CX 0 1
+    M 1
+    DETECTOR rec[-1]
+    R 0 1
+    X_ERROR(0.1) 2
+}
+M 2
+DETECTOR rec[-1]
+"""
+
+ZERO_AFTER_RESET = """REPEAT 5 {
+    R 0 1 2
+    S 0
+    CX 0 1
+    S_DAG 2
+    X_ERROR(0.2) 0 1
+    CZ 1 2
+    M 0 1 2
+    DETECTOR rec[-1]
+    DETECTOR rec[-2]
+    DETECTOR rec[-3]
+}
+"""
+
+
+@pytest.mark.parametrize("name,text", [("error before the loop", ZERO_ENTRY_ERROR),
+                                       ("Cliffords right after resets", ZERO_AFTER_RESET)])
+def test_cliffords_on_zero_qubits(sg, name, text, monkeypatch):
+    """Without the draws, a Clifford op whose qubits are zero in every shot is
+    skipped.  A loop body starting with CX on a qubit that an error before
+    the loop made nonzero must keep it on the first pass (the analysis meets
+    the state before the loop with the state at the end of the body); ops
+    right after a reset are skipped.  Events equal the oracle's and those of
+    the program that keeps every op."""
+    announce("zero qubits", name)
+    (da, oa), (db, ob) = both_ways(sg, text, 21, 4000, monkeypatch)
+    want = oracle.Circuit(text).sample(21, 0, 4000, det=True, obs=True, meas=False)
+    assert np.array_equal(da, want["det"]) and np.array_equal(db, want["det"])
+    assert np.count_nonzero(da) > 0
