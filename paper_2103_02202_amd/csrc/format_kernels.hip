@@ -278,10 +278,14 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v, uint32_t lane
 // in round c / 64, so that each round's output is a contiguous, in-order
 // piece.  WRITE = false: lens[s] = the shot's byte count; WRITE = true: the
 // bytes, at out + offs[s].
+// Set results of one round (64 chunks) a wave formats balanced over its lanes.
+constexpr uint32_t kHitsBuffered = 1024;
+
 template <bool R8, bool WRITE>
 __global__ void __launch_bounds__(256) k_sparse(const uint64_t *__restrict__ T, uint32_t nchunks, uint32_t tstride,
                                                 uint64_t shots, uint64_t rows, uint64_t *__restrict__ lens,
                                                 const uint64_t *__restrict__ offs, uint8_t *__restrict__ out) {
+  __shared__ uint32_t hit_list[R8 ? 1 : 4][R8 ? 1 : kHitsBuffered];   // hits: per wave, one round's results
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t s = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (s >= shots) return;                          // whole waves leave together
@@ -306,6 +310,45 @@ __global__ void __launch_bounds__(256) k_sparse(const uint64_t *__restrict__ T, 
     } else {
       k = wave_exclusive_sum((uint32_t)__builtin_popcountll(x), lane, &hits_total) + nhits_before;
       nhits_before += hits_total;
+    }
+    if (!R8 && hits_total <= kHitsBuffered) {        // uniform
+      // hits, balanced over the lanes: the round's set results go to the
+      // wave's LDS list in order, then lane l formats results l, l + 64, ...
+      // (comma and decimal digits), so that no lane loops over a dense chunk
+      // while the others wait.  (The same for r8, whose results mostly take
+      // one byte each, was slower than its per-lane loop.)
+      uint32_t *list = hit_list[threadIdx.x >> 6];
+      {
+        uint32_t r = k - (nhits_before - hits_total);     // this lane's first rank in the round
+        for (uint64_t m = x; m; m &= m - 1) list[r++] = hit0 + (uint32_t)__builtin_ctzll(m);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t first_rank = nhits_before - hits_total;   // results of the shot before this round
+      for (uint32_t h0 = 0; h0 < hits_total; h0 += 64) {       // uniform
+        const uint32_t h = h0 + lane;
+        const bool valid = h < hits_total;
+        const uint32_t i = valid ? list[h] : 0u;
+        const bool comma = first_rank + h > 0;
+        const uint32_t d = decimal_digits(i);
+        uint32_t run;
+        const uint32_t off = wave_exclusive_sum(valid ? d + (comma ? 1u : 0u) : 0u, lane, &run);
+        if (WRITE && valid) {
+          uint8_t *o = out + base + off;
+          if (comma) *o++ = ',';
+          uint32_t v = i;
+          for (uint32_t q = d; q > 0; q--) {
+            o[q - 1] = (uint8_t)('0' + v % 10u);
+            v /= 10u;
+          }
+        }
+        base += run;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the next round reuses the list
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      continue;
     }
     uint32_t n = 0;
     {
