@@ -214,7 +214,7 @@ template <int T, bool IN_LDS, bool WAVE, bool EVENTS, typename AfterLoads>
 __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                             uint32_t code, uint64_t instr, uint64_t meas, uint64_t *ring,
                                             uint32_t ring_pos, AfterLoads after_loads) {
-  constexpr int V = 2;
+  constexpr int V = WAVE ? 1 : 2;               // one-wave teams: fewer registers, more waves in flight
   const uint32_t s_lo = op.slot0, s_hi = op.slot0 + op.n;
   const uint32_t g_lo = s_lo >> 2, ngroups = ((s_hi - 1) >> 2) - g_lo + 1;
   const uint32_t cand = ngroups * T;
@@ -316,7 +316,7 @@ __device__ __forceinline__ void collapse_op(const FrameParams &p, const Tile<T, 
 template <int T, bool IN_LDS, bool WAVE, uint32_t CODE, typename AfterLoads>
 __device__ __forceinline__ void clifford_op(const FrameParams &p, const Tile<T, IN_LDS> &tl, const DevOp &op,
                                             AfterLoads after_loads) {
-  constexpr int U = 3;
+  constexpr int U = WAVE ? 1 : 3;               // one-wave teams: fewer registers, more waves in flight
   constexpr uint32_t C = T >= 2 ? 2 : 1;          // words per item
   constexpr uint32_t CPT = T / C;                 // items per target
   constexpr bool TWO = CODE == OP_CX || CODE == OP_CY || CODE == OP_CZ || CODE == OP_SWAP;
