@@ -59,11 +59,11 @@ HBM_PEAK_GBS = 8000.0
 # PMC_SOURCES (those the detector step is built from); once any of them
 # changes, `traffic` is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-PMC_KIB = {"k_frame": (360470.3, 1003854.1)}    # FETCH_SIZE KiB, WRITE_SIZE KiB per dispatch
+PMC_KIB = {"k_frame": (360467.1, 1005908.3)}    # FETCH_SIZE KiB, WRITE_SIZE KiB per dispatch
 # SQ counters of the same kernel and workload (per dispatch): what bounds it.
-PMC_SQ = {"SQ_INSTS_VALU": 8.619e8, "SQ_BUSY_CU_CYCLES": 1.531e9, "SQ_LDS_IDX_ACTIVE": 3.960e8,
-          "SQ_LDS_BANK_CONFLICT": 1.825e8, "SQ_WAIT_ANY": 2.761e9, "SQ_WAVE_CYCLES": 6.123e9}
-PMC_SOURCES = "608f6d10e2513a74"                  # sources_digest() when the counters were taken
+PMC_SQ = {"SQ_INSTS_VALU": 8.619e8, "SQ_BUSY_CU_CYCLES": 1.529e9, "SQ_LDS_IDX_ACTIVE": 3.960e8,
+          "SQ_LDS_BANK_CONFLICT": 1.825e8, "SQ_WAIT_ANY": 2.765e9, "SQ_WAVE_CYCLES": 6.115e9}
+PMC_SOURCES = "69a43ed4c65997c2"                  # sources_digest() when the counters were taken
 PMC_PROFILE = "profiles/k_frame_surface_d49_65536shots.md"
 CUS, CLOCK_HZ = 256, 2.4e9
 
